@@ -1,0 +1,139 @@
+"""Pins for the oracle's density pyramid and cone-traced occlusion grids.
+
+Sections "LoD construction" (rho = sum of length * opacity, 2^3 averaging),
+"Shadow simulation" (cone tracing on the density levels) and "Ambient
+occlusion" (density accumulated up to 1 within a radius of influence,
+averaged over the rays). Checked with closed forms and conservation laws.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1801_01155_amd import synth
+
+
+def test_level_dims():
+    dims, loff = O.lod_levels((64, 64, 64))
+    assert dims[:, 0].tolist() == [64, 32, 16, 8, 4, 2, 1]
+    dims, loff = O.lod_levels((5, 3, 2))
+    assert dims.tolist() == [[5, 3, 2], [3, 2, 1], [2, 1, 1], [1, 1, 1]]
+    assert loff.tolist() == [0, 30, 36, 38, 39]
+
+
+def test_single_line_density_closed_form():
+    # one line straight through voxel (1,1,0) along x: length 1, opacity 0.3
+    lat = np.array([[128, 356, 128], [128 + 2 * 256 + 10, 356, 128]], dtype=np.int32)
+    csr = O.voxelize(lat, np.array([0, 2]), np.array([200], np.uint8), (4, 2, 2), 32)
+    lut = synth.lut_constant((1, 1, 1), 0.3)
+    cnt, ln, rho, dims, loff = O.lod(csr, (4, 2, 2), 32, lut, opaque=False)
+    v = 1 + 4 * 1
+    assert cnt[v] == 1.0 and ln[v] == 1.0
+    assert rho[v] == pytest.approx(float(np.float32(0.3)), abs=1e-15)
+    assert cnt[:16].sum() == 1.0
+    # opaque lines have opacity 1
+    _, _, rho1, _, _ = O.lod(csr, (4, 2, 2), 32, lut, opaque=True)
+    assert rho1[v] == 1.0
+    # level 1 cell (0,0,0) covers it: mean of 8 children
+    assert rho[loff[1]] == pytest.approx(float(np.float32(0.3)) / 8, abs=1e-15)
+
+
+def test_diagonal_line_length():
+    # through the corner-free diagonal of voxel (1,1,1): entry bin centres
+    lat = np.array([[128, 300, 300], [128 + 512, 300 + 256, 300 + 256]], dtype=np.int32)
+    csr = O.voxelize(lat, np.array([0, 2]), None, (3, 3, 3), 64)
+    _, ln, _, _, _ = O.lod(csr, (3, 3, 3), 64, synth.lut_constant(), opaque=True)
+    for k, rec in enumerate(csr.records):
+        a, b = O.decode(int(rec), 64)
+        assert ln[np.nonzero(np.diff(csr.offsets.astype(int)))[0][k]] == pytest.approx(
+            np.linalg.norm(b - a), abs=1e-15)
+
+
+@pytest.mark.parametrize("grid", [(32, 32, 32), (13, 7, 5)])
+def test_mass_conservation(grid):
+    rng = np.random.default_rng(3)
+    verts, off = [], [0]
+    for _ in range(80):
+        p = rng.uniform(256, 256 * (np.array(grid) - 1))
+        for _ in range(20):
+            verts.append(np.floor(p).astype(np.int32))
+            p = np.clip(p + rng.normal(size=3) * 200, 256, 256 * (np.array(grid) - 1) - 1)
+        off.append(len(verts))
+    attr = rng.integers(0, 256, 80).astype(np.uint8)
+    csr = O.voxelize(np.array(verts), np.array(off), attr, grid, 16)
+    lut = synth.lut_importance_alpha()
+    cnt, ln, rho, dims, loff = O.lod(csr, grid, 16, lut, opaque=False)
+    assert cnt[:loff[1]].sum() == len(csr.records)
+    for f in (cnt, ln, rho):
+        base = f[:loff[1]].sum()
+        for l in range(1, len(dims)):
+            assert 8.0 ** l * f[loff[l]:loff[l + 1]].sum() == pytest.approx(base, rel=1e-12)
+
+
+# --- cone tracing -----------------------------------------------------------------------
+def _pyramid_const(grid, value):
+    dims, loff = O.lod_levels(grid)
+    return np.full(int(loff[-1]), value)
+
+
+def test_empty_grid_no_occlusion():
+    g = (16, 16, 16)
+    rho = np.zeros(int(O.lod_levels(g)[1][-1]))
+    assert (O.ao_grid(rho, g) == 1.0).all()
+    assert (O.shadow_grid(rho, g, (0.0, 0.6, 0.8)) == 1.0).all()
+
+
+def test_constant_field_cone_closed_form():
+    g = (64, 64, 64)
+    rho0 = 0.01
+    rho = _pyramid_const(g, rho0)
+    p = np.array([32.5, 32.5, 32.5])
+    # AO cone (radius 15): samples at s = 1, 2, 4, 8 with diameters 1, 2, 4, 8
+    for d in O.fibonacci_dirs(16):
+        assert O.cone(rho, g, p, d, 15.0) == pytest.approx(15 * rho0, rel=1e-12)
+    # shadow cone along +x: s = 1 .. 16 inside, s = 32 leaves the grid
+    assert O.cone(rho, g, p, [1, 0, 0], np.inf) == pytest.approx(31 * rho0, rel=1e-12)
+    # accumulation saturates at 1
+    assert O.cone(_pyramid_const(g, 0.5), g, p, [1, 0, 0], np.inf) == 1.0
+    ao = O.ao_grid(rho, g)
+    assert ao.reshape(64, 64, 64)[32, 32, 32] == pytest.approx(1 - 15 * rho0, rel=1e-12)
+
+
+def test_half_space_level0_path_length():
+    # aperture 0 keeps every sample on level 0 with unit steps: occlusion is
+    # rho0 times the number of unit steps taken inside the dense half-space
+    g = (16, 8, 8)
+    dims, loff = O.lod_levels(g)
+    rho = np.zeros(int(loff[-1]))
+    lvl0 = np.zeros((8, 8, 16))
+    lvl0[:, :, :10] = 0.05                      # x < 10 dense
+    rho[:loff[1]] = lvl0.ravel()
+    p = np.array([2.5, 3.5, 3.5])
+    got = O.cone(rho, g, p, [1, 0, 0], np.inf, aperture=0.0)
+    assert got == pytest.approx(0.05 * (9 - 2), rel=1e-12)       # samples at x = 3.5 .. 9.5
+
+
+def test_single_voxel_trilinear_weight():
+    g = (8, 8, 8)
+    dims, loff = O.lod_levels(g)
+    rho = np.zeros(int(loff[-1]))
+    rho[3 + 8 * (3 + 8 * 3)] = 1.0              # voxel (3,3,3), level 0
+    d = np.array([1.0, 1.0, 1.0]) / math.sqrt(3)
+    p = np.array([2.5, 2.5, 2.5])
+    # first sample at s = 1: point p + d, offset 1/sqrt(3) from (2.5,...) toward (3.5,...)
+    f = 1 / math.sqrt(3)
+    got = O.cone(rho, g, p, d, 1.5, aperture=1.0)
+    assert got == pytest.approx(f ** 3, rel=1e-12)
+
+
+def test_ao_grid_on_workload_in_range():
+    w = synth.WORKLOADS["small"]
+    ls = synth.abc_lineset(200, 64, 5)
+    lat, _, _ = O.grid_setup(ls.xyz, 32)
+    csr = O.voxelize(lat, ls.curve_off, ls.attr, 32, 32)
+    cnt, ln, rho, dims, loff = O.lod(csr, 32, 32, synth.lut_importance_alpha(), opaque=False)
+    ao = O.ao_grid(rho, 32, threads=4)
+    sh = O.shadow_grid(rho, 32, synth.LIGHT_DIR, threads=4)
+    assert (ao >= 0).all() and (ao <= 1).all() and ao.min() < 0.99
+    assert (sh >= 0).all() and (sh <= 1).all() and sh.min() < 0.99
