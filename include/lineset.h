@@ -1,0 +1,252 @@
+/*
+ * lineset — voxel-based ray-casting of large 3D line sets on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: Kanzler, Rautenhaus, Westermann, "A Voxel-based Rendering Pipeline
+ * for Large 3D Line Sets". Curves are clipped per voxel, the per-voxel line
+ * endpoints are quantized to N x N bins of the voxel faces and stored in
+ * per-voxel lists; every pixel's ray walks the grid (3D-DDA), intersects the
+ * tubes of the lines in the voxels it visits, sorts those hits per voxel and
+ * composites them front to back with early termination. A density pyramid
+ * drives cone-traced ambient occlusion and soft shadows.
+ *
+ * Conventions for every entry point:
+ *  - Returns an ls_status; on failure nothing is allocated or left half-built
+ *    and ls_last_error() (per thread) describes the cause.
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream). Work is
+ *    enqueued on it; calls that must know device-side sizes synchronise it.
+ *  - Pointers documented as "device" are HIP device (or managed) memory owned
+ *    by the caller, and must stay valid until the stream has passed the call.
+ *  - No exception crosses this boundary.
+ */
+#ifndef LINESET_H
+#define LINESET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LS_OK = 0,
+  LS_EINVAL = -1,        /* invalid argument or input data */
+  LS_ENOMEM = -2,        /* device or host allocation failed, or a size limit */
+  LS_EDEVICE = -3,       /* a HIP runtime call failed */
+  LS_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  LS_EBUSY = -5,         /* server cannot queue the request now */
+  LS_ETIMEOUT = -6       /* wait ended before completion */
+} ls_status;
+
+/* Text of the last non-OK status returned on this thread. Never NULL. */
+const char* ls_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int ls_version(void);
+
+/* An opaque voxelized line set. Owns every device buffer it allocates
+ * (CSR offsets and records, density pyramid, illumination grids) until
+ * lineset_destroy. */
+typedef struct ls_lineset* ls_lineset_t;
+
+/* ------------------------------------------------------------------------ */
+/* Grid set-up (section "Curve voxelization", first paragraph): cube voxels of
+ * side 1; the curves' bounding box is mapped into the grid keeping its aspect
+ * ratio, with one voxel of margin on each side, and every vertex is rounded to
+ * a lattice of 1/256 voxel:
+ *     q = floor((v - lo) * S + 0.5) + 256,
+ *     S = min over axes with extent > 0 of 256 (grid_a - 2) / extent_a,
+ * evaluated in fp64 (S = 0 when all extents are 0).
+ *   xyz       device, float [n_vertices][3]
+ *   lattice   device, int32 [n_vertices][3] (output)
+ *   lo_scale  host, double [4] (output, may be NULL): lo[3], S
+ * Errors: LS_EINVAL for a grid side outside [3, 1024] or a non-finite
+ * coordinate. Synchronises the stream. */
+int lineset_grid_setup(const float* xyz, int64_t n_vertices, const int32_t grid[3],
+                       int32_t* lattice, double* lo_scale, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Voxelization (sections "Curve voxelization", "Line quantization", "GPU
+ * implementation").
+ *
+ * Input curves are vertex sequences: curve c owns vertices
+ * [curve_off[c], curve_off[c+1]). Give either world coordinates (`xyz`,
+ * mapped by the grid set-up above) or lattice coordinates (`lattice`, int32
+ * in 1/256 voxel, each in [0, 256 * grid_a)).
+ *
+ * Each curve segment is clipped against the voxel faces in order of
+ * occurrence (half-open voxels; simultaneous crossings of several planes are
+ * one event whose face is that of the lowest axis). Consecutive events of a
+ * curve bound one per-voxel line; the pieces before the first and after the
+ * last event are dropped, as are lines whose two exact event points or two
+ * quantized endpoints coincide. Endpoints are quantized to the centres of
+ * N x N bins per face: bin = min(floor(local * N), N - 1).
+ *
+ * Output layout (CSR), exported by lineset_export:
+ *   offsets  uint32 [gx*gy*gz + 1], voxel id = x + gx * (y + gy * z)
+ *   records  uint64 [n_records], a voxel's lines consecutive, in order of
+ *            (curve id, position along the curve):
+ *     bits  0..2  entry face   3..8  entry bin u   9..14 entry bin w
+ *     bits 15..17 exit face   18..23 exit bin u   24..29 exit bin w
+ *     bits 32..39 attribute byte   40..63 curve id mod 2^24
+ *   Faces 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; (u, w) are the face's other
+ *   two axes in increasing order.
+ *
+ * Errors: LS_EINVAL for grid sides outside [1, 1024] (3 with xyz input),
+ * more than 2^30 voxels, bins not a power of two in [1, 64], non-monotone
+ * curve_off, a lattice coordinate out of range; LS_ENOMEM if the lines
+ * exceed 2^32 - 1 records or memory runs out. `*out` is NULL on failure.
+ * Synchronises the stream (it reads device-side totals to size buffers). */
+typedef struct {
+  const float* xyz;          /* [n_vertices][3] world coordinates, or NULL */
+  const int32_t* lattice;    /* [n_vertices][3] lattice coordinates, or NULL */
+  const int64_t* curve_off;  /* [n_curves + 1] */
+  const uint8_t* curve_attr; /* [n_curves], or NULL for 255 */
+  int64_t n_vertices;
+  int64_t n_curves;
+  int32_t on_device;         /* 1: the four pointers are device memory; 0: host */
+  int32_t grid[3];
+  int32_t bins;              /* N */
+} ls_voxelize_desc;
+
+int lineset_voxelize(const ls_voxelize_desc* desc, void* hip_stream, ls_lineset_t* out);
+
+void lineset_destroy(ls_lineset_t set);
+
+/* ------------------------------------------------------------------------ */
+/* Density pyramid (section "LoD construction"): per voxel
+ *   count = number of lines, len = sum of line lengths (voxel units),
+ *   rho = sum of length * sigma, sigma = lut[attr].a (1 when opaque);
+ * level l+1 averages the 2^3 children of level l (children beyond an odd side
+ * count as 0), down to 1^3. Stored as float per level.
+ *
+ * Optionally the per-voxel illumination grids (sections "Shadow simulation",
+ * "Ambient occlusion", "Illumination effects"), computed by cone tracing on
+ * rho: from the voxel centre p along direction u, samples at distance s with
+ * cone diameter D = max(1, aperture * s) on level min(L, floor(log2 D))
+ * (cell-centred trilinear, clamp to edge), occlusion += rho * D, s += D, while
+ * s < s_max and the point is inside the grid; occlusion is capped at 1.
+ *   ao[v] = 1 - mean over ao_cones spherical-Fibonacci directions
+ *           (s_max = ao_radius)
+ *   sh[v] = 1 - occlusion towards light_dir (s_max = infinity)
+ *   lut_rgba   device, float [256][4] straight alpha
+ * Errors: LS_EINVAL (bad cone count, radius, aperture or light), LS_ENOMEM. */
+typedef struct {
+  const float* lut_rgba;
+  int32_t opaque;
+  int32_t build_ao;
+  int32_t ao_cones;          /* default 16 */
+  float ao_radius;           /* default 15 voxels */
+  float cone_aperture;       /* default 1: the cone subtends one voxel at s = 1 */
+  int32_t build_shadow;
+  float light_dir[3];        /* unit vector towards a directional light */
+} ls_lod_desc;
+
+int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Rendering (sections "Line Raycasting", "Ray-tube intersections",
+ * "Rendering effects", "Transparency rendering").
+ *
+ * Camera: pixel (i, j), row 0 at the top, sampled at its centre:
+ *   u = 2(i + 0.5)/W - 1, v = 1 - 2(j + 0.5)/H;
+ *   perspective: origin = eye, direction = forward + u right + v up;
+ *   orthographic: origin = eye + u right + v up, direction = forward;
+ * evaluated in fp64 and rounded to fp32 (right/up are half-extent vectors).
+ *
+ * Each ray is clipped to the grid box and walks it voxel by voxel; the next
+ * crossing of axis a is (plane - o_a) * (1 / d_a) in fp64, ties to the lowest
+ * axis. Lines are capsules of `radius` (tube plus joint spheres). mode 0
+ * tests the lines of the visited voxel only and accepts hits with t >= 0
+ * (interactive mode); mode 1 also tests the 26 neighbour voxels and accepts a
+ * hit in the voxel whose [t0, t1) holds its entry t (still-camera mode).
+ * Accepted hits of a voxel are composited in (entry t, record index) order:
+ * with merge_curves, a hit whose entry lies inside the open interval of the
+ * same curve extends it and is not blended again. Colour per fragment:
+ *   shading 0: lut rgb
+ *   shading 1: rgb (ka + kd |n.v|) + ks |n.v|^shininess
+ *   shading 2: rgb (ka AO(x) + kd SH(x) max(0, n.L)) + ks SH(x) max(0, n.h)^shininess
+ * (v towards the eye, h = normalize(L + v), AO/SH trilinear at the entry).
+ * Premultiplied front-to-back: C += (1 - A) a c, A += (1 - A) a; the ray stops
+ * once A >= alpha_stop (opaque lines: a = 1).
+ *   lut_rgba   device, float [256][4] straight alpha
+ *   rgba_out   device, float [height][width][4], premultiplied (C, A)
+ * Errors: LS_EINVAL for a zero or negative size, radius <= 0 (or >= 1 in
+ * mode 1), a zero forward/direction, shading 2 without illumination grids. */
+typedef struct {
+  float eye[3], forward[3], right[3], up[3];
+  int32_t orthographic, width, height;
+} ls_camera;
+
+typedef struct {
+  float radius;
+  int32_t mode;
+  int32_t opaque;
+  float alpha_stop;          /* default 0.95 */
+  int32_t merge_curves;
+  const float* lut_rgba;
+  int32_t shading;
+  float ka, kd, ks, shininess;
+  float light_dir[3];
+} ls_render_params;
+
+int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,
+                   float* rgba_out, void* hip_stream);
+
+/* Same image as lineset_render, with per-frame work counters (host struct,
+ * filled after the call synchronises the stream). */
+typedef struct {
+  int64_t visited;          /* voxels stepped through */
+  int64_t nonempty;         /* visited voxels whose own list is not empty */
+  int64_t tested;           /* ray-capsule tests */
+  int64_t hits;             /* accepted hits */
+  int64_t fragments;        /* composited fragments */
+  int64_t list_bytes;       /* bytes of offsets and records read */
+  int64_t sort_passes;      /* extra passes for voxels with more hits than the sort buffer */
+  int64_t merge_evictions;  /* open intervals evicted from the bounded merge table */
+} ls_render_counters;
+
+int lineset_render_counted(ls_lineset_t set, const ls_camera* cam,
+                           const ls_render_params* params, float* rgba_out,
+                           ls_render_counters* counters, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Inspection. */
+typedef struct {
+  int32_t grid[3];
+  int32_t bins;
+  int64_t n_curves, n_vertices;
+  int64_t n_records;
+  int64_t n_record_slots;    /* records emitted before dropping */
+  int64_t nonempty_voxels;
+  int64_t max_list;          /* longest per-voxel list */
+  int32_t n_levels;          /* density pyramid levels (0 before build_lod) */
+  int32_t has_ao, has_shadow;
+  int32_t level_dims[32][3];
+  int64_t level_off[33];
+  double lo_scale[4];        /* grid set-up of xyz input: lo[3], S */
+  size_t device_bytes;       /* bytes held by the set */
+} ls_info;
+
+int lineset_info(ls_lineset_t set, ls_info* out);
+
+enum {
+  LS_EXPORT_OFFSETS = 0,     /* uint32 [voxels + 1] */
+  LS_EXPORT_RECORDS = 1,     /* uint64 [n_records] */
+  LS_EXPORT_LOD_COUNT = 2,   /* float, all levels flat (level_off) */
+  LS_EXPORT_LOD_LEN = 3,
+  LS_EXPORT_LOD_RHO = 4,
+  LS_EXPORT_AO = 5,          /* float [voxels] */
+  LS_EXPORT_SHADOW = 6       /* float [voxels] */
+};
+
+/* Copies one buffer of the set into `dst` (host or device). Errors:
+ * LS_EINVAL if the buffer does not exist or dst_bytes is too small. */
+int lineset_export(ls_lineset_t set, int32_t what, void* dst, size_t dst_bytes,
+                   int32_t dst_on_device, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINESET_H */

@@ -130,8 +130,9 @@ int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* att
   if (bins < 1 || bins > 64 || (bins & (bins - 1))) return -1;
   int64_t nvox = (int64_t)grid[0] * grid[1] * grid[2];
   int64_t nv = n_curves > 0 ? curve_off[n_curves] : 0;
+  if (n_curves > 0 && curve_off[0] != 0) return -1;
   for (int64_t c = 0; c < n_curves; ++c)
-    if (curve_off[c + 1] < curve_off[c] || curve_off[c] < 0) return -1;
+    if (curve_off[c + 1] < curve_off[c]) return -1;
   for (int64_t v = 0; v < nv; ++v)
     for (int a = 0; a < 3; ++a)
       if (lat[3 * v + a] < 0 || lat[3 * v + a] >= 256 * grid[a]) return -1;
@@ -502,7 +503,8 @@ static void dda_init(dda_state* s, const int32_t grid[3], const float of[3], con
     s->R[a] = grid[a];
     s->o[a] = (double)of[a];
     double d = (double)df[a];
-    if (d != 0.0) {
+    /* an axis whose 1/d overflows is treated as parallel to the ray */
+    if (d != 0.0 && !isinf(1.0 / d)) {
       s->inv[a] = 1.0 / d;
       double ta = (0.0 - s->o[a]) * s->inv[a];
       double tb = ((double)grid[a] - s->o[a]) * s->inv[a];

@@ -1,0 +1,283 @@
+"""Python binding of liblineset (include/lineset.h): argument marshalling only.
+
+Every step of the rendering pipeline runs in the HIP library; this module
+converts torch tensors (device memory) and the current HIP stream into the
+C-ABI's plain pointers and maps status codes to exceptions. Functions carry
+the C names. Loading fails loudly when the library has not been built:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblineset.so")
+
+LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EUNSUPPORTED, LS_EBUSY, LS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+EXPORT_OFFSETS, EXPORT_RECORDS, EXPORT_LOD_COUNT, EXPORT_LOD_LEN, EXPORT_LOD_RHO, EXPORT_AO, EXPORT_SHADOW = range(7)
+
+
+class LinesetError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class VoxelizeDesc(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("lattice", C.c_void_p), ("curve_off", C.c_void_p),
+                ("curve_attr", C.c_void_p), ("n_vertices", C.c_int64), ("n_curves", C.c_int64),
+                ("on_device", C.c_int32), ("grid", C.c_int32 * 3), ("bins", C.c_int32)]
+
+
+class LodDesc(C.Structure):
+    _fields_ = [("lut_rgba", C.c_void_p), ("opaque", C.c_int32), ("build_ao", C.c_int32),
+                ("ao_cones", C.c_int32), ("ao_radius", C.c_float), ("cone_aperture", C.c_float),
+                ("build_shadow", C.c_int32), ("light_dir", C.c_float * 3)]
+
+
+class CameraS(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("forward", C.c_float * 3), ("right", C.c_float * 3),
+                ("up", C.c_float * 3), ("orthographic", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("radius", C.c_float), ("mode", C.c_int32), ("opaque", C.c_int32),
+                ("alpha_stop", C.c_float), ("merge_curves", C.c_int32), ("lut_rgba", C.c_void_p),
+                ("shading", C.c_int32), ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
+                ("shininess", C.c_float), ("light_dir", C.c_float * 3)]
+
+
+class RenderCounters(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("visited", "nonempty", "tested", "hits", "fragments",
+                                          "list_bytes", "sort_passes", "merge_evictions")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("grid", C.c_int32 * 3), ("bins", C.c_int32), ("n_curves", C.c_int64),
+                ("n_vertices", C.c_int64), ("n_records", C.c_int64),
+                ("n_record_slots", C.c_int64), ("nonempty_voxels", C.c_int64),
+                ("max_list", C.c_int64), ("n_levels", C.c_int32), ("has_ao", C.c_int32),
+                ("has_shadow", C.c_int32), ("level_dims", (C.c_int32 * 3) * 32),
+                ("level_off", C.c_int64 * 33), ("lo_scale", C.c_double * 4),
+                ("device_bytes", C.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"liblineset.so not built ({LIB_PATH}); run "
+                              "`python -m paper_1801_01155_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.ls_last_error.restype = C.c_char_p
+        L.lineset_voxelize.argtypes = [C.POINTER(VoxelizeDesc), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.lineset_destroy.argtypes = [C.c_void_p]
+        L.lineset_destroy.restype = None
+        L.lineset_build_lod.argtypes = [C.c_void_p, C.POINTER(LodDesc), C.c_void_p]
+        L.lineset_render.argtypes = [C.c_void_p, C.POINTER(CameraS), C.POINTER(RenderParams),
+                                     C.c_void_p, C.c_void_p]
+        L.lineset_render_counted.argtypes = [C.c_void_p, C.POINTER(CameraS),
+                                             C.POINTER(RenderParams), C.c_void_p,
+                                             C.POINTER(RenderCounters), C.c_void_p]
+        L.lineset_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+        L.lineset_export.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_int32,
+                                     C.c_void_p]
+        L.lineset_grid_setup.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.c_void_p,
+                                         C.POINTER(C.c_double), C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LS_OK:
+        raise LinesetError(rc, lib().ls_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _grid3(grid):
+    g = [int(grid)] * 3 if isinstance(grid, int) else [int(x) for x in grid]
+    return (C.c_int32 * 3)(*g)
+
+
+# ---------------------------------------------------------------------------
+# C entry points, same names
+
+def lineset_grid_setup(xyz, grid, stream=None):
+    """Device float [V,3] -> device int32 [V,3] lattice; returns (lattice, lo_scale)."""
+    xyz = _dev(xyz, torch.float32)
+    lat = torch.empty(xyz.shape, dtype=torch.int32, device=xyz.device)
+    ls = (C.c_double * 4)()
+    _check(lib().lineset_grid_setup(_ptr(xyz), xyz.shape[0], _grid3(grid), _ptr(lat), ls,
+                                    _stream(stream)))
+    return lat, list(ls)
+
+
+class LineSet:
+    """Owns an ls_lineset_t handle."""
+
+    def __init__(self, handle):
+        self.handle = C.c_void_p(handle)
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.lineset_destroy(self.handle)
+        self.handle = None
+
+    def info(self) -> Info:
+        return lineset_info(self)
+
+
+def lineset_voxelize(curve_off, grid, bins=32, xyz=None, lattice=None, attr=None,
+                     stream=None) -> LineSet:
+    d = VoxelizeDesc()
+    keep = []
+    if xyz is not None:
+        xyz = _dev(xyz, torch.float32)
+        keep.append(xyz)
+        d.xyz = xyz.data_ptr()
+        d.n_vertices = xyz.shape[0]
+    if lattice is not None:
+        lattice = _dev(lattice, torch.int32)
+        keep.append(lattice)
+        d.lattice = lattice.data_ptr()
+        d.n_vertices = lattice.shape[0]
+    off = _dev(curve_off, torch.int64)
+    keep.append(off)
+    d.curve_off = off.data_ptr()
+    d.n_curves = off.shape[0] - 1
+    if attr is not None:
+        attr = _dev(attr, torch.uint8)
+        keep.append(attr)
+        d.curve_attr = attr.data_ptr()
+    d.on_device = 1
+    d.grid = _grid3(grid)
+    d.bins = bins
+    h = C.c_void_p()
+    _check(lib().lineset_voxelize(C.byref(d), _stream(stream), C.byref(h)))
+    return LineSet(h.value)
+
+
+def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=16,
+                      ao_radius=15.0, cone_aperture=1.0, build_shadow=False,
+                      light_dir=(0.0, 0.0, 1.0), stream=None):
+    lut = _dev(lut, torch.float32)
+    d = LodDesc()
+    d.lut_rgba = lut.data_ptr()
+    d.opaque = int(opaque)
+    d.build_ao = int(build_ao)
+    d.ao_cones = ao_cones
+    d.ao_radius = ao_radius
+    d.cone_aperture = cone_aperture
+    d.build_shadow = int(build_shadow)
+    d.light_dir = (C.c_float * 3)(*light_dir)
+    _check(lib().lineset_build_lod(ls.handle, C.byref(d), _stream(stream)))
+
+
+def camera_struct(cam) -> CameraS:
+    c = CameraS()
+    c.eye = (C.c_float * 3)(*cam.eye)
+    c.forward = (C.c_float * 3)(*cam.forward)
+    c.right = (C.c_float * 3)(*cam.right)
+    c.up = (C.c_float * 3)(*cam.up)
+    c.orthographic = int(cam.orthographic)
+    c.width = cam.width
+    c.height = cam.height
+    return c
+
+
+def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
+                  shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
+                  light_dir=(0.0, 0.0, 1.0)) -> RenderParams:
+    p = RenderParams()
+    p.radius = radius
+    p.mode = mode
+    p.opaque = int(opaque)
+    p.alpha_stop = alpha_stop
+    p.merge_curves = int(merge_curves)
+    p.lut_rgba = lut.data_ptr()
+    p.shading = shading
+    p.ka, p.kd, p.ks, p.shininess = ka, kd, ks, shininess
+    p.light_dir = (C.c_float * 3)(*light_dir)
+    return p
+
+
+def lineset_render(ls: LineSet, cam, lut, out=None, stream=None, **params):
+    """Renders into a device float tensor [H, W, 4] (premultiplied RGBA)."""
+    lut = _dev(lut, torch.float32)
+    if out is None:
+        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+    c = camera_struct(cam)
+    p = render_params(lut, **params)
+    _check(lib().lineset_render(ls.handle, C.byref(c), C.byref(p), _ptr(out), _stream(stream)))
+    return out
+
+
+def lineset_render_counted(ls: LineSet, cam, lut, out=None, stream=None, **params):
+    lut = _dev(lut, torch.float32)
+    if out is None:
+        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+    c = camera_struct(cam)
+    p = render_params(lut, **params)
+    k = RenderCounters()
+    _check(lib().lineset_render_counted(ls.handle, C.byref(c), C.byref(p), _ptr(out),
+                                        C.byref(k), _stream(stream)))
+    return out, k.as_dict()
+
+
+def lineset_info(ls: LineSet) -> Info:
+    i = Info()
+    _check(lib().lineset_info(ls.handle, C.byref(i)))
+    return i
+
+
+_EXPORT_DTYPE = {EXPORT_OFFSETS: torch.int32, EXPORT_RECORDS: torch.int64,
+                 EXPORT_LOD_COUNT: torch.float32, EXPORT_LOD_LEN: torch.float32,
+                 EXPORT_LOD_RHO: torch.float32, EXPORT_AO: torch.float32,
+                 EXPORT_SHADOW: torch.float32}
+
+
+def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
+    """Copies a buffer of the set into a new device tensor (offsets as int32
+    bit patterns of uint32, records as int64 bit patterns of uint64)."""
+    i = lineset_info(ls)
+    nvox = i.grid[0] * i.grid[1] * i.grid[2]
+    n = {EXPORT_OFFSETS: nvox + 1, EXPORT_RECORDS: i.n_records,
+         EXPORT_LOD_COUNT: i.level_off[i.n_levels] if i.n_levels else 0,
+         EXPORT_LOD_LEN: i.level_off[i.n_levels] if i.n_levels else 0,
+         EXPORT_LOD_RHO: i.level_off[i.n_levels] if i.n_levels else 0,
+         EXPORT_AO: nvox, EXPORT_SHADOW: nvox}[what]
+    t = torch.empty(max(int(n), 1), dtype=_EXPORT_DTYPE[what], device="cuda")
+    _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
+                                _stream(stream)))
+    return t[:n]

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP translation units of liblineset.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "lineset.h"
+
+#define LS_MAX_LEVELS 32
+#define LS_INVALID_VOXEL 0xFFFFFFFFu
+
+// ---------------------------------------------------------------------------
+// Error reporting (per-thread text behind ls_last_error).
+void ls_set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define LS_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ls_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                     \
+      return LS_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// The line set object behind ls_lineset_t.
+struct ls_lineset {
+  int32_t grid[3];
+  int32_t bins;
+  int64_t nvox;
+  int64_t n_curves, n_vertices;
+  int64_t n_records, n_slots;
+  int64_t nonempty, max_list;
+  uint32_t* offsets;   // [nvox + 1]
+  uint64_t* records;   // [n_records] (at least one element allocated)
+  uint64_t* occupancy; // 1 bit per 4^3 macro cell: any record inside
+  int32_t macro[3];    // macro-cell grid dims (ceil(grid / 4))
+  // density pyramid
+  int32_t n_levels;
+  int32_t level_dims[LS_MAX_LEVELS][3];
+  int64_t level_off[LS_MAX_LEVELS + 1];
+  float* lod_count;
+  float* lod_len;
+  float* lod_rho;
+  float* ao;
+  float* sh;
+  double lo_scale[4];
+  size_t bytes;
+  int device;
+};
+
+// Device allocation tracked on the set.
+int ls_alloc(ls_lineset* s, void** p, size_t bytes);
+void ls_free_all(ls_lineset* s);
+
+// ---------------------------------------------------------------------------
+// Scans (scan.hip). out may alias in; writes n + 1 values (out[n] = total).
+// `block_sums` needs scan_block_sums_len(n) elements of T.
+int64_t scan_block_sums_len(int64_t n);
+int exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums,
+                       hipStream_t st);
+int exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* block_sums,
+                       hipStream_t st);
+
+// Fill kernels (no hipMemset, so callers may capture them in graphs).
+int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Voxelization (vox.hip).
+struct SnapArgs {
+  double lo[3];
+  double scale;
+};
+
+int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream_t st);
+double vox_scale(const double lo[3], const double hi[3], const int32_t grid[3]);
+int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_t st);
+int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
+              const uint8_t* attr, SnapArgs sa, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Density pyramid and illumination (lod.hip, illum.hip).
+void lod_plan(const int32_t grid[3], int32_t* n_levels, int32_t dims[][3], int64_t* level_off);
+int lod_build(ls_lineset* s, const float* lut, int opaque, hipStream_t st);
+int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st);
+int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Rendering (render.hip).
+struct RenderCounters {
+  unsigned long long visited, nonempty, tested, hits, fragments, list_bytes, sort_passes,
+      merge_evictions;
+};
+
+int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
+                 float* out, RenderCounters* dev_counters, hipStream_t st);

@@ -1,0 +1,722 @@
+// Ray-casting of the voxelized line set on gfx950 (sections "Line
+// Raycasting", "Ray-tube intersections", "Rendering effects", "Transparency
+// rendering").
+//
+// One ray per lane; a workgroup of 256 lanes renders a 16 x 16 screen tile as
+// four 8 x 8 wave tiles, so the 64 rays of a wave walk nearly the same voxels
+// and their list loads coalesce in the L1/L2. Workgroups are mapped to tiles
+// so that each of the 8 XCDs (one L2 each) renders one horizontal band of the
+// screen rather than every 8th tile.
+//
+// Per ray:
+//  1. ray from the camera in fp64, rounded to fp32 (these fp32 values are the
+//     ray);
+//  2. clip to the grid box and walk it voxel by voxel (3D-DDA) with the
+//     next crossing of each axis t = (plane - o) * (1/d) in fp64, ties to the
+//     lowest axis: voxel order and [t0, t1) match the CPU oracle bit for bit;
+//  3. per non-empty voxel, capsule tests in fp32 in a voxel-local frame
+//     (origin = ray point at t0 minus the voxel corner, formed in fp64);
+//  4. accepted hits go into an 8-slot register-resident sorted buffer keyed
+//     by (entry t, record index); a voxel with more hits is swept again for
+//     the next 8 (rare);
+//  5. per hit in order: per-curve interval merge in an 8-entry register
+//     table (the oldest interval is evicted when full), shading, premultiplied
+//     front-to-back compositing, termination at alpha_stop.
+#include "ls_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSortSlots = 8;
+constexpr int kMergeSlots = 8;
+constexpr int kXcds = 8;
+
+struct RenderArgs {
+  const uint32_t* offsets;
+  const uint64_t* records;
+  int32_t g[3];
+  float inv_bins;
+  const float* lut;
+  const float* ao;
+  const float* sh;
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t ortho, W, H;
+  float radius, r2, alpha_stop;
+  int32_t opaque, merge, shading;
+  float ka, kd, ks, shin;
+  float light[3];
+  float* out;
+  RenderCounters* counters;
+  int32_t tiles_x, n_tiles, tiles_per_xcd;
+};
+
+struct Counts {
+  uint32_t visited = 0, nonempty = 0, tested = 0, hits = 0, fragments = 0, passes = 0,
+           evictions = 0;
+  uint32_t list_bytes = 0;
+};
+
+__device__ inline void decode_point(uint32_t code, float inv_bins, float p[3]) {
+  const int face = (int)(code & 7u);
+  const int axis = face >> 1;
+  const float side = (float)(face & 1);
+  const float u = ((float)((code >> 3) & 63u) + 0.5f) * inv_bins;
+  const float w = ((float)((code >> 9) & 63u) + 0.5f) * inv_bins;
+  p[0] = axis == 0 ? side : u;
+  p[1] = axis == 1 ? side : (axis == 0 ? u : w);
+  p[2] = axis == 2 ? side : w;
+}
+
+__device__ inline float dot3(const float a[3], const float b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Ray vs capsule {x : dist(x, ab) <= r}: [min entry, max exit] over the two
+// spheres and the finite cylinder. q, d in the voxel-local frame.
+__device__ inline bool capsule(const float q[3], const float d[3], float dd, float inv_dd,
+                               const float a[3], const float b[3], float r2, float& t_in,
+                               float& t_out) {
+  float lo = INFINITY, hi = -INFINITY;
+  float oa[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+  float ob[3] = {q[0] - b[0], q[1] - b[1], q[2] - b[2]};
+  {
+    float B = dot3(oa, d), C = dot3(oa, oa) - r2;
+    float disc = B * B - dd * C;
+    if (disc >= 0.f) {
+      float s = __builtin_sqrtf(disc);
+      lo = fminf(lo, (-B - s) * inv_dd);
+      hi = fmaxf(hi, (-B + s) * inv_dd);
+    }
+  }
+  {
+    float B = dot3(ob, d), C = dot3(ob, ob) - r2;
+    float disc = B * B - dd * C;
+    if (disc >= 0.f) {
+      float s = __builtin_sqrtf(disc);
+      lo = fminf(lo, (-B - s) * inv_dd);
+      hi = fmaxf(hi, (-B + s) * inv_dd);
+    }
+  }
+  float ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  float L2 = dot3(ba, ba);
+  float iL2 = rcp(L2);
+  float dba = dot3(d, ba), oba = dot3(oa, ba);
+  float kd = dba * iL2, ko = oba * iL2;
+  float dp[3] = {d[0] - kd * ba[0], d[1] - kd * ba[1], d[2] - kd * ba[2]};
+  float op[3] = {oa[0] - ko * ba[0], oa[1] - ko * ba[1], oa[2] - ko * ba[2]};
+  float A = dot3(dp, dp);
+  if (A > 0.f) {
+    float B = dot3(op, dp), C = dot3(op, op) - r2;
+    float disc = B * B - A * C;
+    if (disc >= 0.f) {
+      float s = __builtin_sqrtf(disc);
+      float iA = rcp(A);
+      float c0 = (-B - s) * iA, c1 = (-B + s) * iA;
+      float s0, s1;
+      if (dba != 0.f) {
+        float idba = rcp(dba);
+        float u0 = -oba * idba, u1 = (L2 - oba) * idba;
+        s0 = fminf(u0, u1);
+        s1 = fmaxf(u0, u1);
+      } else if (oba >= 0.f && oba <= L2) {
+        s0 = -INFINITY;
+        s1 = INFINITY;
+      } else {
+        s0 = INFINITY;
+        s1 = -INFINITY;
+      }
+      float e0 = fmaxf(c0, s0), e1 = fminf(c1, s1);
+      if (e0 <= e1) {
+        lo = fminf(lo, e0);
+        hi = fmaxf(hi, e1);
+      }
+    }
+  }
+  t_in = lo;
+  t_out = hi;
+  return lo <= hi;
+}
+
+// Trilinear, cell-centred, clamp-to-edge lookup of a per-voxel grid at the
+// point cell + p (p local).
+__device__ inline float grid_lookup(const float* grid, const int32_t g[3], const int32_t cell[3],
+                                    const float p[3]) {
+  int32_t i0[3], i1[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float x = p[a] - 0.5f;
+    float fl = floorf(x);
+    f[a] = x - fl;
+    int32_t lo = cell[a] + (int32_t)fl;
+    int32_t hi = lo + 1;
+    lo = lo < 0 ? 0 : (lo > g[a] - 1 ? g[a] - 1 : lo);
+    hi = hi < 0 ? 0 : (hi > g[a] - 1 ? g[a] - 1 : hi);
+    i0[a] = lo;
+    i1[a] = hi;
+  }
+  const int64_t sy = g[0], sz = (int64_t)g[0] * g[1];
+  const int64_t z0 = i0[2] * sz, z1 = i1[2] * sz, y0 = i0[1] * sy, y1 = i1[1] * sy;
+  float c00 = grid[i0[0] + y0 + z0] * (1.f - f[0]) + grid[i1[0] + y0 + z0] * f[0];
+  float c10 = grid[i0[0] + y1 + z0] * (1.f - f[0]) + grid[i1[0] + y1 + z0] * f[0];
+  float c01 = grid[i0[0] + y0 + z1] * (1.f - f[0]) + grid[i1[0] + y0 + z1] * f[0];
+  float c11 = grid[i0[0] + y1 + z1] * (1.f - f[0]) + grid[i1[0] + y1 + z1] * f[0];
+  float c0 = c00 * (1.f - f[1]) + c10 * f[1];
+  float c1 = c01 * (1.f - f[1]) + c11 * f[1];
+  return c0 * (1.f - f[2]) + c1 * f[2];
+}
+
+// Per-ray compositing state.
+struct Accum {
+  float C[3] = {0.f, 0.f, 0.f};
+  float A = 0.f;
+  bool done = false;
+  uint32_t mt_tag[kMergeSlots];
+  double mt_out[kMergeSlots];
+  __device__ Accum() {
+#pragma unroll
+    for (int m = 0; m < kMergeSlots; ++m) {
+      mt_tag[m] = 0xFFFFFFFFu;
+      mt_out[m] = -INFINITY;
+    }
+  }
+};
+
+// Returns true if the hit merges into an open interval of its curve.
+__device__ inline bool merge_hit(Accum& acc, uint32_t tag, double t_in, double t_out,
+                                 Counts& cnt) {
+  int f = -1;
+#pragma unroll
+  for (int m = 0; m < kMergeSlots; ++m)
+    if (acc.mt_tag[m] == tag) f = m;
+  if (f >= 0) {
+    bool inside = false;
+#pragma unroll
+    for (int m = 0; m < kMergeSlots; ++m) {
+      if (m == f) {
+        inside = t_in <= acc.mt_out[m];
+        acc.mt_out[m] = inside ? fmax(acc.mt_out[m], t_out) : t_out;
+      }
+    }
+    return inside;
+  }
+  // new curve: take an empty slot, else evict the interval that closed first
+  int slot = 0;
+  double best = acc.mt_out[0];
+#pragma unroll
+  for (int m = 1; m < kMergeSlots; ++m)
+    if (acc.mt_out[m] < best) {
+      best = acc.mt_out[m];
+      slot = m;
+    }
+#pragma unroll
+  for (int m = 0; m < kMergeSlots; ++m) {
+    if (m == slot) {
+      if (acc.mt_tag[m] != 0xFFFFFFFFu) cnt.evictions++;
+      acc.mt_tag[m] = tag;
+      acc.mt_out[m] = t_out;
+    }
+  }
+  return false;
+}
+
+struct Shade {
+  float v[3];   // towards the eye, unit
+  float h[3];   // half vector for the directional light
+};
+
+// Shade and composite one fragment. p is the entry point in the frame of
+// `cell`, a/b the record's endpoints in the same frame.
+__device__ inline void composite(const RenderArgs& R, const Shade& S, Accum& acc, uint64_t rec,
+                                 const int32_t cell[3], const float p[3], const float a[3],
+                                 const float b[3], Counts& cnt) {
+  const int attr = (int)((rec >> 32) & 0xFF);
+  const float4 lut = reinterpret_cast<const float4*>(R.lut)[attr];
+  const float alpha = R.opaque ? 1.f : lut.w;
+  float col[3] = {lut.x, lut.y, lut.z};
+  if (R.shading != 0) {
+    float ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    float pa[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+    float u = dot3(pa, ba) * rcp(dot3(ba, ba));
+    u = fminf(fmaxf(u, 0.f), 1.f);
+    float n[3] = {pa[0] - u * ba[0], pa[1] - u * ba[1], pa[2] - u * ba[2]};
+    float nl = dot3(n, n);
+    float inl = nl > 0.f ? __builtin_amdgcn_rsqf(nl) : 0.f;
+    n[0] *= inl;
+    n[1] *= inl;
+    n[2] *= inl;
+    if (R.shading == 1) {
+      float ndv = fabsf(dot3(n, S.v));
+      float spec = R.ks * __builtin_amdgcn_exp2f(R.shin * __builtin_amdgcn_logf(ndv));
+      spec = ndv > 0.f ? spec : 0.f;
+      float diff = R.ka + R.kd * ndv;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) col[c] = col[c] * diff + spec;
+    } else {
+      float aov = grid_lookup(R.ao, R.g, cell, p);
+      float shv = grid_lookup(R.sh, R.g, cell, p);
+      float ndl = fmaxf(dot3(n, R.light), 0.f);
+      float ndh = fmaxf(dot3(n, S.h), 0.f);
+      float spec = R.ks * shv * __builtin_amdgcn_exp2f(R.shin * __builtin_amdgcn_logf(ndh));
+      spec = ndh > 0.f ? spec : 0.f;
+      float diff = R.ka * aov + R.kd * shv * ndl;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) col[c] = col[c] * diff + spec;
+    }
+  }
+  const float w = (1.f - acc.A) * alpha;
+  acc.C[0] += w * col[0];
+  acc.C[1] += w * col[1];
+  acc.C[2] += w * col[2];
+  acc.A += w;
+  cnt.fragments++;
+  if (acc.A >= R.alpha_stop) acc.done = true;
+}
+
+// Sorted register buffer of hits. Key (t, idx) lexicographic.
+template <typename TKey>
+struct HitBuf {
+  TKey t[kSortSlots];
+  float so[kSortSlots];
+  uint32_t idx[kSortSlots];
+  uint32_t aux[kSortSlots];
+  int n = 0;
+  int dropped = 0;
+
+  __device__ inline static bool less(TKey ta, uint32_t ia, TKey tb, uint32_t ib) {
+    return ta < tb || (ta == tb && ia < ib);
+  }
+
+  __device__ inline void insert(TKey tk, float sout, uint32_t id, uint32_t ax) {
+    if (n == kSortSlots && !less(tk, id, t[kSortSlots - 1], idx[kSortSlots - 1])) {
+      ++dropped;
+      return;
+    }
+    if (n == kSortSlots) ++dropped;
+    // carry the new entry down the sorted array, swapping with larger keys
+#pragma unroll
+    for (int i = 0; i < kSortSlots; ++i) {
+      bool occupied = i < n;
+      bool sw = !occupied || less(tk, id, t[i], idx[i]);
+      if (sw) {
+        TKey t2 = t[i];
+        float s2 = so[i];
+        uint32_t i2 = idx[i], a2 = aux[i];
+        t[i] = tk;
+        so[i] = sout;
+        idx[i] = id;
+        aux[i] = ax;
+        tk = t2;
+        sout = s2;
+        id = i2;
+        ax = a2;
+        if (!occupied) break;
+      }
+    }
+    if (n < kSortSlots) ++n;
+  }
+};
+
+struct Ray {
+  float o[3], d[3];
+  double od[3], inv[3];
+  double tnext[3];
+  int32_t cell[3];
+  int32_t step[3];
+  double t0;
+  bool alive;
+};
+
+__device__ inline void make_ray(const RenderArgs& R, int i, int j, float o[3], float d[3]) {
+  double u = __dadd_rn(__ddiv_rn(__dmul_rn(2.0, __dadd_rn((double)i, 0.5)), (double)R.W), -1.0);
+  double v = __dadd_rn(1.0, -__ddiv_rn(__dmul_rn(2.0, __dadd_rn((double)j, 0.5)), (double)R.H));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double su = __dmul_rn(u, (double)R.right[a]);
+    double sv = __dmul_rn(v, (double)R.up[a]);
+    if (R.ortho) {
+      o[a] = (float)__dadd_rn(__dadd_rn((double)R.eye[a], su), sv);
+      d[a] = R.fwd[a];
+    } else {
+      o[a] = R.eye[a];
+      d[a] = (float)__dadd_rn(__dadd_rn((double)R.fwd[a], su), sv);
+    }
+  }
+}
+
+__device__ inline void dda_init(const RenderArgs& R, Ray& ray) {
+  double tn = 0.0, tf = INFINITY;
+  ray.alive = false;
+  if (ray.d[0] == 0.f && ray.d[1] == 0.f && ray.d[2] == 0.f) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ray.od[a] = (double)ray.o[a];
+    double d = (double)ray.d[a];
+    const double inv = __ddiv_rn(1.0, d);
+    // an axis whose 1/d overflows (d == 0 or denormal) is parallel to the ray
+    if (d != 0.0 && !isinf(inv)) {
+      ray.inv[a] = inv;
+      double ta = __dmul_rn(__dadd_rn(0.0, -ray.od[a]), ray.inv[a]);
+      double tb = __dmul_rn(__dadd_rn((double)R.g[a], -ray.od[a]), ray.inv[a]);
+      double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+      tn = lo > tn ? lo : tn;
+      tf = hi < tf ? hi : tf;
+      ray.step[a] = d > 0.0 ? 1 : -1;
+    } else {
+      ray.inv[a] = 0.0;
+      ray.step[a] = 0;
+      if (!(ray.od[a] >= 0.0 && ray.od[a] < (double)R.g[a])) tf = -INFINITY;
+    }
+  }
+  if (!(tn < tf)) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double p = __dadd_rn(ray.od[a], __dmul_rn((double)ray.d[a], tn));
+    double fl = floor(p);
+    int32_t c = fl < 0.0 ? 0 : (fl > (double)(R.g[a] - 1) ? R.g[a] - 1 : (int32_t)fl);
+    ray.cell[a] = c;
+    if (ray.step[a] > 0)
+      ray.tnext[a] = __dmul_rn(__dadd_rn((double)(c + 1), -ray.od[a]), ray.inv[a]);
+    else if (ray.step[a] < 0)
+      ray.tnext[a] = __dmul_rn(__dadd_rn((double)c, -ray.od[a]), ray.inv[a]);
+    else
+      ray.tnext[a] = INFINITY;
+  }
+  ray.t0 = tn;
+  ray.alive = true;
+}
+
+// Advance to the next voxel; returns the t1 of the voxel just left.
+__device__ inline double dda_step(const RenderArgs& R, Ray& ray) {
+  int a = 0;
+  if (ray.tnext[1] < ray.tnext[0]) a = 1;
+  if (ray.tnext[2] < (a == 0 ? ray.tnext[0] : ray.tnext[1])) a = 2;
+  double t1;
+  if (a == 0) {
+    t1 = ray.tnext[0];
+    ray.cell[0] += ray.step[0];
+    if (ray.cell[0] < 0 || ray.cell[0] >= R.g[0]) ray.alive = false;
+    double plane = (double)(ray.step[0] > 0 ? ray.cell[0] + 1 : ray.cell[0]);
+    ray.tnext[0] = __dmul_rn(__dadd_rn(plane, -ray.od[0]), ray.inv[0]);
+  } else if (a == 1) {
+    t1 = ray.tnext[1];
+    ray.cell[1] += ray.step[1];
+    if (ray.cell[1] < 0 || ray.cell[1] >= R.g[1]) ray.alive = false;
+    double plane = (double)(ray.step[1] > 0 ? ray.cell[1] + 1 : ray.cell[1]);
+    ray.tnext[1] = __dmul_rn(__dadd_rn(plane, -ray.od[1]), ray.inv[1]);
+  } else {
+    t1 = ray.tnext[2];
+    ray.cell[2] += ray.step[2];
+    if (ray.cell[2] < 0 || ray.cell[2] >= R.g[2]) ray.alive = false;
+    double plane = (double)(ray.step[2] > 0 ? ray.cell[2] + 1 : ray.cell[2]);
+    ray.tnext[2] = __dmul_rn(__dadd_rn(plane, -ray.od[2]), ray.inv[2]);
+  }
+  return t1;
+}
+
+__device__ inline double peek_t1(const Ray& ray) {
+  double m = ray.tnext[0];
+  m = ray.tnext[1] < m ? ray.tnext[1] : m;
+  m = ray.tnext[2] < m ? ray.tnext[2] : m;
+  return m;
+}
+
+__device__ inline void local_origin(const Ray& ray, double t, const int32_t cell[3], float q[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q[a] = (float)(fma(t, (double)ray.d[a], ray.od[a]) - (double)cell[a]);
+}
+
+// Own-list mode: test the voxel's lines, accept t >= 0, composite in
+// (t, index) order.
+__device__ inline void voxel_fast(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+                                  float inv_dd, uint32_t lo, uint32_t hi, Accum& acc,
+                                  Counts& cnt) {
+  float q[3];
+  local_origin(ray, ray.t0, ray.cell, q);
+  const float s_min = (float)(-ray.t0);  // t >= 0  <=>  s >= -t0
+  if (R.opaque) {
+    float best = INFINITY;
+    uint32_t bi = 0xFFFFFFFFu;
+    for (uint32_t k = lo; k < hi; ++k) {
+      const uint64_t rec = R.records[k];
+      float a[3], b[3], si, so;
+      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+      cnt.tested++;
+      if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && ray.t0 + (double)si >= 0.0) {
+        cnt.hits++;
+        if (si < best || (si == best && k < bi)) {
+          best = si;
+          bi = k;
+        }
+      }
+    }
+    cnt.list_bytes += 8u * (hi - lo);
+    if (bi != 0xFFFFFFFFu) {
+      const uint64_t rec = R.records[bi];
+      float a[3], b[3], p[3];
+      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
+      composite(R, S, acc, rec, ray.cell, p, a, b, cnt);
+      acc.done = true;
+    }
+    (void)s_min;
+    return;
+  }
+  float last_t = -INFINITY;
+  uint32_t last_i = 0;
+  bool first = true;
+  for (;;) {
+    HitBuf<float> buf;
+    for (uint32_t k = lo; k < hi; ++k) {
+      const uint64_t rec = R.records[k];
+      float a[3], b[3], si, so;
+      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+      cnt.tested++;
+      if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
+      if (!(ray.t0 + (double)si >= 0.0)) continue;
+      if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
+      if (first) cnt.hits++;
+      buf.insert(si, so, k, 0u);
+    }
+    cnt.list_bytes += 8u * (hi - lo);
+#pragma unroll
+    for (int m = 0; m < kSortSlots; ++m) {
+      if (m >= buf.n || acc.done) break;
+      const uint64_t rec = R.records[buf.idx[m]];
+      if (R.merge) {
+        const uint32_t tag = (uint32_t)(rec >> 40);
+        if (merge_hit(acc, tag, ray.t0 + (double)buf.t[m], ray.t0 + (double)buf.so[m], cnt))
+          continue;
+      }
+      float a[3], b[3], p[3];
+      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c] = q[c] + buf.t[m] * ray.d[c];
+      composite(R, S, acc, rec, ray.cell, p, a, b, cnt);
+    }
+    if (acc.done || buf.dropped == 0) break;
+    last_t = buf.t[kSortSlots - 1];
+    last_i = buf.idx[kSortSlots - 1];
+    first = false;
+    cnt.passes++;
+  }
+}
+
+// Neighbour mode: lines of the 27 voxels around the visited one; a hit is
+// accepted by the visited voxel whose [t0, t1) holds its entry t. Each
+// line's t is computed in the frame of its own voxel, with the origin at the
+// ray point nearest the voxel centre, so every visited voxel sees the same t
+// for a line and the hits are partitioned exactly.
+__device__ inline double owner_ref(const Ray& ray, const int32_t w[3], double idd) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s += ((double)w[a] + 0.5 - ray.od[a]) * (double)ray.d[a];
+  return s * idd;
+}
+
+__device__ inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+                                   float inv_dd, double idd, double t1, Accum& acc, Counts& cnt) {
+  double last_t = -INFINITY;
+  uint32_t last_i = 0;
+  bool first = true;
+  for (;;) {
+    HitBuf<double> buf;
+    for (int nb = 0; nb < 27; ++nb) {
+      int32_t w[3] = {ray.cell[0] + nb % 3 - 1, ray.cell[1] + (nb / 3) % 3 - 1,
+                      ray.cell[2] + nb / 9 - 1};
+      if (w[0] < 0 || w[1] < 0 || w[2] < 0 || w[0] >= R.g[0] || w[1] >= R.g[1] || w[2] >= R.g[2])
+        continue;
+      const int64_t vid = w[0] + (int64_t)R.g[0] * (w[1] + (int64_t)R.g[1] * w[2]);
+      const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
+      cnt.list_bytes += 8u + 8u * (hi - lo);
+      if (lo == hi) continue;
+      const double tr = owner_ref(ray, w, idd);
+      float q[3];
+      local_origin(ray, tr, w, q);
+      for (uint32_t k = lo; k < hi; ++k) {
+        const uint64_t rec = R.records[k];
+        float a[3], b[3], si, so;
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+        cnt.tested++;
+        if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
+        const double ti = tr + (double)si;
+        if (!(ti >= ray.t0 && ti < t1)) continue;
+        if (!first && !HitBuf<double>::less(last_t, last_i, ti, k)) continue;
+        if (first) cnt.hits++;
+        buf.insert(ti, (float)(tr + (double)so - ti), k, (uint32_t)nb);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kSortSlots; ++m) {
+      if (m >= buf.n || acc.done) break;
+      const uint64_t rec = R.records[buf.idx[m]];
+      if (!R.opaque && R.merge) {
+        const uint32_t tag = (uint32_t)(rec >> 40);
+        if (merge_hit(acc, tag, buf.t[m], buf.t[m] + (double)buf.so[m], cnt)) continue;
+      }
+      const int nb = (int)buf.aux[m];
+      int32_t w[3] = {ray.cell[0] + nb % 3 - 1, ray.cell[1] + (nb / 3) % 3 - 1,
+                      ray.cell[2] + nb / 9 - 1};
+      const double tr = owner_ref(ray, w, idd);
+      float q[3], a[3], b[3], p[3];
+      local_origin(ray, tr, w, q);
+      const float s_in = (float)(buf.t[m] - tr);
+      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c] = q[c] + s_in * ray.d[c];
+      composite(R, S, acc, rec, w, p, a, b, cnt);
+      if (R.opaque) acc.done = true;
+    }
+    if (acc.done || buf.dropped == 0) break;
+    last_t = buf.t[kSortSlots - 1];
+    last_i = buf.idx[kSortSlots - 1];
+    first = false;
+    cnt.passes++;
+  }
+}
+
+__device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
+  unsigned long long v[8] = {c.visited, c.nonempty, c.tested, c.hits, c.fragments, c.list_bytes,
+                             c.passes, c.evictions};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    unsigned long long x = v[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    v[k] = x;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&out->visited, v[0]);
+    atomicAdd(&out->nonempty, v[1]);
+    atomicAdd(&out->tested, v[2]);
+    atomicAdd(&out->hits, v[3]);
+    atomicAdd(&out->fragments, v[4]);
+    atomicAdd(&out->list_bytes, v[5]);
+    atomicAdd(&out->sort_passes, v[6]);
+    atomicAdd(&out->merge_evictions, v[7]);
+  }
+}
+
+template <int kMode>
+__device__ inline void render_pixel(const RenderArgs& R, int i, int j, Counts& cnt) {
+  Ray ray;
+  make_ray(R, i, j, ray.o, ray.d);
+  dda_init(R, ray);
+  Accum acc;
+  if (ray.alive) {
+    const float dd = dot3(ray.d, ray.d);
+    const float inv_dd = 1.f / dd;
+    const double idd = 1.0 / ((double)ray.d[0] * ray.d[0] + (double)ray.d[1] * ray.d[1] +
+                              (double)ray.d[2] * ray.d[2]);
+    Shade S;
+    const float il = __builtin_amdgcn_rsqf(dd);
+    S.v[0] = -ray.d[0] * il;
+    S.v[1] = -ray.d[1] * il;
+    S.v[2] = -ray.d[2] * il;
+    float h[3] = {R.light[0] + S.v[0], R.light[1] + S.v[1], R.light[2] + S.v[2]};
+    float hl = dot3(h, h);
+    float ih = hl > 0.f ? __builtin_amdgcn_rsqf(hl) : 0.f;
+    S.h[0] = h[0] * ih;
+    S.h[1] = h[1] * ih;
+    S.h[2] = h[2] * ih;
+    // every step moves one cell monotonically along one axis: at most
+    // gx + gy + gz steps (the cap only guards against malformed input)
+    const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
+    for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
+      cnt.visited++;
+      if (kMode == 0) {
+        const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+        const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
+        cnt.list_bytes += 8u;
+        if (hi > lo) {
+          cnt.nonempty++;
+          voxel_fast(R, ray, S, dd, inv_dd, lo, hi, acc, cnt);
+        }
+      } else {
+        const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+        if (R.offsets[vid + 1] > R.offsets[vid]) cnt.nonempty++;
+        voxel_exact(R, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
+      }
+      ray.t0 = dda_step(R, ray);
+    }
+  }
+  float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
+  reinterpret_cast<float4*>(R.out)[(int64_t)j * R.W + i] = px;
+}
+
+template <int kMode, bool kCount>
+__global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
+  // XCD-banded tile order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous run of tiles.
+  const int b = blockIdx.x;
+  const int tile = (b % kXcds) * R.tiles_per_xcd + b / kXcds;
+  Counts cnt;
+  if (tile < R.n_tiles) {
+    const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (i < R.W && j < R.H) render_pixel<kMode>(R, i, j, cnt);
+  }
+  if (kCount) flush_counts(R.counters, cnt);
+}
+
+}  // namespace
+
+int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p, float* out,
+                 RenderCounters* dev_counters, hipStream_t st) {
+  RenderArgs R{};
+  R.offsets = s->offsets;
+  R.records = s->records;
+  for (int a = 0; a < 3; ++a) {
+    R.g[a] = s->grid[a];
+    R.eye[a] = cam->eye[a];
+    R.fwd[a] = cam->forward[a];
+    R.right[a] = cam->right[a];
+    R.up[a] = cam->up[a];
+    R.light[a] = p->light_dir[a];
+  }
+  R.inv_bins = 1.0f / (float)s->bins;
+  R.lut = p->lut_rgba;
+  R.ao = s->ao;
+  R.sh = s->sh;
+  R.ortho = cam->orthographic;
+  R.W = cam->width;
+  R.H = cam->height;
+  R.radius = p->radius;
+  R.r2 = p->radius * p->radius;
+  R.alpha_stop = p->alpha_stop;
+  R.opaque = p->opaque;
+  R.merge = p->merge_curves;
+  R.shading = p->shading;
+  R.ka = p->ka;
+  R.kd = p->kd;
+  R.ks = p->ks;
+  R.shin = p->shininess;
+  R.out = out;
+  R.counters = dev_counters;
+  R.tiles_x = (R.W + 15) / 16;
+  const int tiles_y = (R.H + 15) / 16;
+  R.n_tiles = R.tiles_x * tiles_y;
+  R.tiles_per_xcd = (R.n_tiles + kXcds - 1) / kXcds;
+  const unsigned blocks = (unsigned)(R.tiles_per_xcd * kXcds);
+  const bool count = dev_counters != nullptr;
+  if (p->mode == 0) {
+    if (count) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(kBlock), 0, st, R);
+    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(kBlock), 0, st, R);
+  } else {
+    if (count) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(kBlock), 0, st, R);
+    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(kBlock), 0, st, R);
+  }
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}

@@ -1,0 +1,550 @@
+// Voxelization of curves into per-voxel quantized line lists (CSR) on gfx950.
+//
+// Sections "Curve voxelization", "Line quantization" and "GPU
+// implementation". The paper's GPU construction appends per-curve lines
+// tagged with voxel ids, sorts by voxel and prefix-sums the counts. Here the
+// append is replaced by a count pass that sizes every curve's output range
+// exactly (so the emit pass writes without global atomics on a cursor), the
+// sort by a histogram + scan + scatter, and determinism inside a voxel by a
+// rank pass:
+//   k_count   thread per curve: upper bound of the curve's lines (plane
+//             crossings - 1); validates the input
+//   scan      curve ranges
+//   k_emit    thread per curve: exact integer clipping, quantization and
+//             packing; writes (voxel, record) in curve order and takes the
+//             record's slot in its voxel with one atomic on the histogram
+//   scan      voxel offsets (CSR)
+//   k_scatter thread per emitted line: index into its voxel's range
+//   k_rank    thread per CSR slot: ranks the voxel's lines by emission order
+//             and gathers the record, so each list is in (curve, position
+//             along curve) order regardless of atomic order
+// All arithmetic deciding a line's voxel, faces and bins is exact integer
+// arithmetic on the 1/256-voxel lattice.
+#include "ls_internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct GridArgs {
+  int32_t g[3];
+  int32_t bins;
+  int32_t bin_shift;  // log2(256 / bins)
+};
+
+// Grid set-up (section "Curve voxelization"): fp64 without contraction, the
+// same expression as documented in lineset.h.
+__device__ inline int32_t snap_coord(float x, double lo, double scale) {
+  double y = __dmul_rn(__dadd_rn((double)x, -lo), scale);
+  y = __dadd_rn(y, 0.5);
+  return (int32_t)floor(y) + 256;
+}
+
+template <bool kFloatIn>
+__device__ inline void load_vertex(const float* xyz, const int32_t* lat, int64_t v,
+                                   const SnapArgs& sa, int32_t q[3]) {
+  if (kFloatIn) {
+    const float* p = xyz + 3 * v;
+    q[0] = snap_coord(p[0], sa.lo[0], sa.scale);
+    q[1] = snap_coord(p[1], sa.lo[1], sa.scale);
+    q[2] = snap_coord(p[2], sa.lo[2], sa.scale);
+  } else {
+    const int32_t* p = lat + 3 * v;
+    q[0] = p[0];
+    q[1] = p[1];
+    q[2] = p[2];
+  }
+}
+
+__device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
+  return q[0] >= 0 && q[1] >= 0 && q[2] >= 0 && q[0] < 256 * ga.g[0] && q[1] < 256 * ga.g[1] &&
+         q[2] < 256 * ga.g[2];
+}
+
+// error codes written to err[0]
+constexpr int kErrOffsets = 1;
+constexpr int kErrRange = 2;
+
+template <bool kFloatIn>
+__global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_t* lat,
+                                                  const int64_t* curve_off, int64_t n_curves,
+                                                  int64_t n_vertices, SnapArgs sa, GridArgs ga,
+                                                  uint64_t* slots, int* err) {
+  int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n_curves) return;
+  int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
+  if (v0 < 0 || v1 < v0 || v1 > n_vertices || (c == 0 && v0 != 0)) {
+    atomicOr(err, kErrOffsets);
+    slots[c] = 0;
+    return;
+  }
+  uint64_t crossings = 0;
+  int32_t q[3], cell[3];
+  if (v1 > v0) {
+    load_vertex<kFloatIn>(xyz, lat, v0, sa, q);
+    if (!in_range(q, ga)) atomicOr(err, kErrRange);
+    cell[0] = q[0] >> 8;
+    cell[1] = q[1] >> 8;
+    cell[2] = q[2] >> 8;
+  }
+  for (int64_t v = v0 + 1; v < v1; ++v) {
+    load_vertex<kFloatIn>(xyz, lat, v, sa, q);
+    if (!in_range(q, ga)) atomicOr(err, kErrRange);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int32_t nc = q[a] >> 8;
+      crossings += (uint64_t)abs(nc - cell[a]);
+      cell[a] = nc;
+    }
+  }
+  slots[c] = crossings > 0 ? crossings - 1 : 0;
+}
+
+// floor(num / den) for 0 <= num < 2^31, 0 < den < 2^31, without an integer
+// divide: fp64 quotient, corrected by one step either way.
+__device__ inline int64_t floor_div_pos(int64_t num, int64_t den) {
+  int64_t q = (int64_t)((double)num / (double)den);
+  if (q * den > num) --q;
+  else if ((q + 1) * den <= num) ++q;
+  return q;
+}
+
+// In-face bins of an event point on voxel `cell`, face normal `axis`.
+// xn = event point * den (exact), local coordinate = xn - 256 cell den in [0, 256 den].
+__device__ inline uint32_t face_code(int axis, int side, const int64_t xn[3], int64_t den,
+                                     const int32_t cell[3], const GridArgs& ga) {
+  const int ua = axis == 0 ? 1 : 0;
+  const int wa = axis == 2 ? 1 : 2;
+  const int64_t step = den << ga.bin_shift;  // den * 256 / N
+  int64_t lu = xn[ua] - ((int64_t)cell[ua] << 8) * den;
+  int64_t lw = xn[wa] - ((int64_t)cell[wa] << 8) * den;
+  int64_t bu = floor_div_pos(lu, step);
+  int64_t bw = floor_div_pos(lw, step);
+  bu = bu < ga.bins - 1 ? bu : ga.bins - 1;
+  bw = bw < ga.bins - 1 ? bw : ga.bins - 1;
+  return (uint32_t)(2 * axis + side) | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
+}
+
+struct Event {
+  int64_t xn[3];
+  int64_t den;
+  uint32_t entry_code;
+};
+
+template <bool kFloatIn>
+__global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t* lat,
+                                                 const int64_t* curve_off, const uint8_t* attr,
+                                                 int64_t n_curves, SnapArgs sa, GridArgs ga,
+                                                 const uint64_t* slot_off, uint64_t* rec_out,
+                                                 uint32_t* vox_out, uint32_t* rank_out,
+                                                 uint32_t* hist) {
+  int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n_curves) return;
+  int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
+  uint64_t w = slot_off[c];
+  const uint64_t w_end = slot_off[c + 1];
+  const uint64_t hi_bits = ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)(c & 0xFFFFFF) << 40);
+  const int64_t gx = ga.g[0], gxy = (int64_t)ga.g[0] * ga.g[1];
+  Event prev;
+  bool have_prev = false;
+  int32_t P0[3], P1[3], cell[3];
+  if (v1 - v0 >= 2) {
+    load_vertex<kFloatIn>(xyz, lat, v0, sa, P0);
+    cell[0] = P0[0] >> 8;
+    cell[1] = P0[1] >> 8;
+    cell[2] = P0[2] >> 8;
+  }
+  for (int64_t v = v0 + 1; v < v1; ++v) {
+    load_vertex<kFloatIn>(xyz, lat, v, sa, P1);
+    int64_t d[3], k[3];
+    int32_t left[3];
+    int sg[3];
+    bool any = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d[a] = (int64_t)P1[a] - P0[a];
+      int32_t c0 = P0[a] >> 8, c1 = P1[a] >> 8;
+      sg[a] = d[a] > 0 ? 1 : (d[a] < 0 ? -1 : 0);
+      k[a] = d[a] > 0 ? c0 + 1 : c0;
+      left[a] = abs(c1 - c0);
+      any |= left[a] != 0;
+    }
+    while (any) {
+      // crossing parameter of each axis: t_a = num_a / den_a, den_a = |d_a|
+      int64_t num[3], dn[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        num[a] = sg[a] > 0 ? 256 * k[a] - P0[a] : P0[a] - 256 * k[a];
+        dn[a] = sg[a] > 0 ? d[a] : -d[a];
+      }
+      int best = -1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (left[a] == 0) continue;
+        if (best < 0 || num[a] * dn[best] < num[best] * dn[a]) best = a;
+      }
+      bool grp[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        grp[a] = left[a] != 0 && (a == best || num[a] * dn[best] == num[best] * dn[a]);
+      const int fa = grp[0] ? 0 : (grp[1] ? 1 : 2);
+      int32_t ncell[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ncell[a] = cell[a] + (grp[a] ? sg[a] : 0);
+      Event ev;
+      ev.den = dn[fa];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + num[fa] * d[b];
+      const int exit_side = sg[fa] > 0 ? 1 : 0;
+      const uint32_t exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
+      ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
+      if (have_prev && w < w_end) {
+        bool same = prev.xn[0] * ev.den == ev.xn[0] * prev.den &&
+                    prev.xn[1] * ev.den == ev.xn[1] * prev.den &&
+                    prev.xn[2] * ev.den == ev.xn[2] * prev.den;
+        if (same || prev.entry_code == exit_code) {
+          vox_out[w] = LS_INVALID_VOXEL;
+        } else {
+          uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
+          rec_out[w] = (uint64_t)prev.entry_code | ((uint64_t)exit_code << 15) | hi_bits;
+          vox_out[w] = vid;
+          rank_out[w] = atomicAdd(hist + vid, 1u);
+        }
+        ++w;
+      }
+      prev = ev;
+      have_prev = true;
+      any = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cell[a] = ncell[a];
+        if (grp[a]) {
+          --left[a];
+          k[a] += sg[a];
+        }
+        any |= left[a] != 0;
+      }
+    }
+    P0[0] = P1[0];
+    P0[1] = P1[1];
+    P0[2] = P1[2];
+  }
+  for (; w < w_end; ++w) vox_out[w] = LS_INVALID_VOXEL;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const uint32_t* rank,
+                                                    int64_t n_slots, const uint32_t* offsets,
+                                                    uint32_t* idx) {
+  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n_slots) return;
+  uint32_t v = vox[e];
+  if (v == LS_INVALID_VOXEL) return;
+  idx[offsets[v] + rank[e]] = (uint32_t)e;
+}
+
+// Each CSR slot p holds some emitted line e of voxel v; its final position is
+// offsets[v] + (number of lines of v emitted before e).
+__global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint32_t* vox,
+                                                 const uint64_t* rec, int64_t n_records,
+                                                 const uint32_t* offsets, uint64_t* records) {
+  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n_records) return;
+  uint32_t e = idx[p];
+  uint32_t v = vox[e];
+  uint32_t lo = offsets[v], hi = offsets[v + 1];
+  uint32_t r = 0;
+  for (uint32_t q = lo; q < hi; ++q) r += idx[q] < e;
+  records[lo + r] = rec[e];
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_stats(const uint32_t* offsets, int64_t nvox,
+                                                       unsigned long long* nonempty,
+                                                       unsigned int* max_list) {
+  int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned n = 0;
+  if (v < nvox) n = offsets[v + 1] - offsets[v];
+  unsigned long long ne = n > 0;
+  unsigned mx = n;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    ne += __shfl_xor(ne, d, 64);
+    unsigned o = __shfl_xor(mx, d, 64);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (ne) atomicAdd(nonempty, ne);
+    if (mx) atomicMax(max_list, mx);
+  }
+}
+
+// Occupancy of 4^3 macro cells (empty-space skipping in the ray caster).
+__global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, GridArgs ga,
+                                                      int32_t mx, int32_t my, int32_t mz,
+                                                      unsigned long long* occ) {
+  int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t nm = (int64_t)mx * my * mz;
+  if (m >= nm) return;
+  int32_t bx = (int32_t)(m % mx), by = (int32_t)((m / mx) % my), bz = (int32_t)(m / ((int64_t)mx * my));
+  bool any = false;
+  for (int z = 4 * bz; z < 4 * bz + 4 && z < ga.g[2] && !any; ++z)
+    for (int y = 4 * by; y < 4 * by + 4 && y < ga.g[1] && !any; ++y)
+      for (int x = 4 * bx; x < 4 * bx + 4 && x < ga.g[0]; ++x) {
+        int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
+        if (offsets[v + 1] > offsets[v]) {
+          any = true;
+          break;
+        }
+      }
+  if (any) atomicOr(occ + (m >> 6), 1ull << (m & 63));
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bbox(const float* xyz, int64_t nv, double* part,
+                                                 int* bad) {
+  __shared__ double s[6][kBlock];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nv;
+       v += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double x = (double)xyz[3 * v + a];
+      if (!isfinite(x)) *bad = 1;
+      lo[a] = fmin(lo[a], x);
+      hi[a] = fmax(hi[a], x);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a][threadIdx.x] = lo[a];
+    s[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = fmin(s[a][threadIdx.x], s[a][threadIdx.x + st]);
+        s[3 + a][threadIdx.x] = fmax(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + st]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 6; ++a) part[6 * blockIdx.x + a] = s[a][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_snap(const float* xyz, int64_t nv, SnapArgs sa,
+                                                 int32_t* lat) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= 3 * nv) return;
+  int a = (int)(i % 3);
+  lat[i] = snap_coord(xyz[i], sa.lo[a], sa.scale);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+struct DeviceBuf {
+  void* p = nullptr;
+  ~DeviceBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      ls_set_error("device allocation of %zu bytes failed", bytes);
+      return LS_ENOMEM;
+    }
+    return LS_OK;
+  }
+  template <typename T>
+  T* as() { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream_t st) {
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = 0.0;
+    hi[a] = 0.0;
+  }
+  if (nv <= 0) return LS_OK;
+  int64_t blocks = (nv + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  DeviceBuf part, bad;
+  int rc;
+  if ((rc = part.alloc(sizeof(double) * 6 * blocks)) || (rc = bad.alloc(sizeof(int)))) return rc;
+  LS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_bbox, dim3((unsigned)blocks), dim3(kBlock), 0, st, xyz, nv,
+                     part.as<double>(), bad.as<int>());
+  LS_HIP(hipGetLastError());
+  std::vector<double> h(6 * blocks);
+  int hbad = 0;
+  LS_HIP(hipMemcpyAsync(h.data(), part.p, sizeof(double) * 6 * blocks, hipMemcpyDeviceToHost, st));
+  LS_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  LS_HIP(hipStreamSynchronize(st));
+  if (hbad) {
+    ls_set_error("non-finite vertex coordinate");
+    return LS_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = INFINITY;
+    hi[a] = -INFINITY;
+  }
+  for (int64_t b = 0; b < blocks; ++b)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::fmin(lo[a], h[6 * b + a]);
+      hi[a] = std::fmax(hi[a], h[6 * b + 3 + a]);
+    }
+  return LS_OK;
+}
+
+double vox_scale(const double lo[3], const double hi[3], const int32_t grid[3]) {
+  double s = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    volatile double ext = hi[a] - lo[a];
+    if (ext > 0) {
+      volatile double num = 256.0 * (double)(grid[a] - 2);
+      volatile double cand = num / ext;
+      if (cand < s) s = cand;
+    }
+  }
+  return std::isinf(s) ? 0.0 : s;
+}
+
+int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_t st) {
+  if (nv <= 0) return LS_OK;
+  hipLaunchKernelGGL(k_snap, dim3(blocks_for(3 * nv)), dim3(kBlock), 0, st, xyz, nv, sa, lat);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
+              const uint8_t* attr, SnapArgs sa, hipStream_t st) {
+  GridArgs ga;
+  for (int a = 0; a < 3; ++a) ga.g[a] = s->grid[a];
+  ga.bins = s->bins;
+  int sh = 0;
+  while ((256 >> sh) > s->bins) ++sh;
+  ga.bin_shift = sh;  // 256 / bins = 2^sh
+  const int64_t C = s->n_curves;
+  const bool float_in = xyz != nullptr;
+  int rc;
+
+  // 1. per-curve slot counts + validation
+  DeviceBuf slots, err, sums64;
+  if ((rc = slots.alloc(sizeof(uint64_t) * (C + 1))) || (rc = err.alloc(sizeof(int))) ||
+      (rc = sums64.alloc(sizeof(uint64_t) * scan_block_sums_len(C))))
+    return rc;
+  LS_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  if (C > 0) {
+    if (float_in)
+      hipLaunchKernelGGL((k_count<true>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+                         curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
+    else
+      hipLaunchKernelGGL((k_count<false>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+                         curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
+    LS_HIP(hipGetLastError());
+  }
+  if ((rc = exclusive_scan_u64(slots.as<uint64_t>(), slots.as<uint64_t>(), C, sums64.as<uint64_t>(),
+                               st)))
+    return rc;
+  uint64_t n_slots = 0;
+  int herr = 0;
+  LS_HIP(hipMemcpyAsync(&n_slots, slots.as<uint64_t>() + C, sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, st));
+  LS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  LS_HIP(hipStreamSynchronize(st));
+  if (herr & kErrOffsets) {
+    ls_set_error("curve_off must start at 0, be non-decreasing and end at most at n_vertices");
+    return LS_EINVAL;
+  }
+  if (herr & kErrRange) {
+    ls_set_error("a vertex lies outside [0, 256 * grid) in lattice units");
+    return LS_EINVAL;
+  }
+  if (n_slots >= 0xFFFFFFFFull) {
+    ls_set_error("too many per-voxel lines (%llu slots >= 2^32 - 1)", (unsigned long long)n_slots);
+    return LS_ENOMEM;
+  }
+  s->n_slots = (int64_t)n_slots;
+
+  // 2. offsets array (owned by the set) doubles as the histogram
+  if ((rc = ls_alloc(s, (void**)&s->offsets, sizeof(uint32_t) * (s->nvox + 1)))) return rc;
+  if ((rc = fill_u32(s->offsets, 0u, s->nvox + 1, st))) return rc;
+
+  // 3. emit
+  DeviceBuf rec, vox, rank, sums32;
+  if ((rc = rec.alloc(sizeof(uint64_t) * n_slots)) || (rc = vox.alloc(sizeof(uint32_t) * n_slots)) ||
+      (rc = rank.alloc(sizeof(uint32_t) * n_slots)) ||
+      (rc = sums32.alloc(sizeof(uint32_t) * scan_block_sums_len(s->nvox))))
+    return rc;
+  if (C > 0) {
+    if (float_in)
+      hipLaunchKernelGGL((k_emit<true>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+                         curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
+    else
+      hipLaunchKernelGGL((k_emit<false>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+                         curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
+    LS_HIP(hipGetLastError());
+  }
+
+  // 4. counts -> offsets (in place)
+  if ((rc = exclusive_scan_u32(s->offsets, s->offsets, s->nvox, sums32.as<uint32_t>(), st)))
+    return rc;
+  uint32_t n_rec = 0;
+  LS_HIP(hipMemcpyAsync(&n_rec, s->offsets + s->nvox, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  LS_HIP(hipStreamSynchronize(st));
+  s->n_records = n_rec;
+
+  // 5. scatter + rank/gather into the set's record array
+  if ((rc = ls_alloc(s, (void**)&s->records, sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
+  DeviceBuf idx;
+  if ((rc = idx.alloc(sizeof(uint32_t) * (n_rec ? n_rec : 1)))) return rc;
+  if (n_slots > 0) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for((int64_t)n_slots)), dim3(kBlock), 0, st,
+                       vox.as<uint32_t>(), rank.as<uint32_t>(), (int64_t)n_slots, s->offsets,
+                       idx.as<uint32_t>());
+    LS_HIP(hipGetLastError());
+  }
+  if (n_rec > 0) {
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(n_rec)), dim3(kBlock), 0, st, idx.as<uint32_t>(),
+                       vox.as<uint32_t>(), rec.as<uint64_t>(), (int64_t)n_rec, s->offsets,
+                       s->records);
+    LS_HIP(hipGetLastError());
+  }
+
+  // 6. list statistics and macro-cell occupancy
+  DeviceBuf stats;
+  if ((rc = stats.alloc(16))) return rc;
+  LS_HIP(hipMemsetAsync(stats.p, 0, 16, st));
+  hipLaunchKernelGGL(k_list_stats, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, s->offsets,
+                     s->nvox, stats.as<unsigned long long>(),
+                     (unsigned int*)(stats.as<char>() + 8));
+  LS_HIP(hipGetLastError());
+  for (int a = 0; a < 3; ++a) s->macro[a] = (s->grid[a] + 3) / 4;
+  int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
+  int64_t words = (nm + 63) / 64;
+  if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * words))) return rc;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(words)), dim3(kBlock), 0, st,
+                     (unsigned long long*)s->occupancy, words);
+  LS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nm)), dim3(kBlock), 0, st, s->offsets, ga,
+                     s->macro[0], s->macro[1], s->macro[2], (unsigned long long*)s->occupancy);
+  LS_HIP(hipGetLastError());
+  unsigned long long hstats[2] = {0, 0};
+  LS_HIP(hipMemcpyAsync(hstats, stats.p, 16, hipMemcpyDeviceToHost, st));
+  LS_HIP(hipStreamSynchronize(st));
+  s->nonempty = (int64_t)hstats[0];
+  s->max_list = (int64_t)(uint32_t)hstats[1];
+  return LS_OK;
+}

@@ -1,0 +1,124 @@
+"""GPU parity: grid set-up, voxelization (CSR) and the density pyramid /
+illumination grids against the oracle. Integer outputs are bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1801_01155_amd as L
+from paper_1801_01155_amd import synth
+from tests import gpu_util as U
+from tests.test_oracle_voxelize import _random_curves
+
+pytestmark = pytest.mark.gpu
+
+
+def _csr_equal(ls, ref, label):
+    offs, recs = U.gpu_csr(ls)
+    print(f"[csr {label}] records gpu={len(recs)} oracle={len(ref.records)}", flush=True)
+    assert np.array_equal(offs, ref.offsets), f"{label}: offsets differ"
+    assert np.array_equal(recs, ref.records), f"{label}: records differ"
+
+
+def test_grid_setup_bit_exact():
+    w, ls = U.workload("small")
+    for grid in ((64, 64, 64), (37, 64, 20)):
+        lat, lo_scale = L.lineset_grid_setup(U.dev(ls.xyz), grid)
+        ref, lo, s = O.grid_setup(ls.xyz, grid)
+        assert np.array_equal(lat.cpu().numpy(), ref)
+        assert lo_scale[3] == s and list(lo_scale[:3]) == list(lo)
+
+
+def test_voxelize_small_workload_from_xyz():
+    w, ls = U.workload("small")
+    ref, _ = U.oracle_csr_from_xyz(ls, w["grid"], w["bins"])
+    s = L.lineset_voxelize(ls.curve_off, w["grid"], w["bins"], xyz=ls.xyz, attr=ls.attr)
+    _csr_equal(s, ref, "small")
+    info = s.info()
+    cnt = np.diff(ref.offsets.astype(np.int64))
+    assert info.nonempty_voxels == int((cnt > 0).sum()) and info.max_list == int(cnt.max())
+
+
+@pytest.mark.parametrize("seed,step,bins", [(1, 64, 4), (2, 32, 32), (3, 1, 8), (4, 128, 64),
+                                            (5, 16, 1), (6, 7, 16)])
+def test_voxelize_edge_corner_cases(seed, step, bins):
+    rng = np.random.default_rng(seed)
+    grid = (5, 4, 6)
+    lat, off = _random_curves(rng, 300, grid, step)
+    attr = rng.integers(0, 256, len(off) - 1).astype(np.uint8)
+    ref = O.voxelize(lat, off, attr, grid, bins)
+    s = L.lineset_voxelize(off, grid, bins, lattice=lat, attr=attr)
+    _csr_equal(s, ref, f"random seed={seed} step={step} bins={bins}")
+
+
+def test_voxelize_medium_perturbed_and_deterministic():
+    # 4000 x 200 perturbed streamlines on 96^3: many tiles, ragged tails
+    ls = synth.abc_lineset(4000, 200, 12, perturb=True)
+    ref, lat = U.oracle_csr_from_xyz(ls, 96, 32)
+    a = L.lineset_voxelize(ls.curve_off, 96, 32, xyz=ls.xyz, attr=ls.attr)
+    _csr_equal(a, ref, "medium xyz")
+    b = L.lineset_voxelize(ls.curve_off, 96, 32, lattice=lat, attr=ls.attr)
+    _csr_equal(b, ref, "medium lattice")
+
+
+def test_voxelize_degenerate_inputs():
+    # no curves, single-vertex curves, curves that never leave a voxel
+    grid = (8, 8, 8)
+    s = L.lineset_voxelize(np.array([0], np.int64), grid, 32, lattice=np.zeros((0, 3), np.int32))
+    assert s.info().n_records == 0
+    lat = np.array([[300, 300, 300], [310, 320, 330], [600, 600, 600]], np.int32)
+    off = np.array([0, 1, 1, 3], np.int64)
+    s = L.lineset_voxelize(off, grid, 32, lattice=lat)
+    _csr_equal(s, O.voxelize(lat, off, None, grid, 32), "degenerate")
+
+
+def test_voxelize_rejects_bad_input():
+    lat = np.array([[0, 0, 0], [256 * 8, 0, 0]], np.int32)
+    with pytest.raises(L.LinesetError):
+        L.lineset_voxelize(np.array([0, 2]), (8, 8, 8), 32, lattice=lat)
+    with pytest.raises(L.LinesetError):
+        L.lineset_voxelize(np.array([0, 2]), (8, 8, 8), 24, lattice=lat[:1].repeat(2, 0))
+    with pytest.raises(L.LinesetError):
+        L.lineset_voxelize(np.array([1, 2]), (8, 8, 8), 32, lattice=lat[:1].repeat(2, 0))
+
+
+# --- density pyramid and illumination grids ----------------------------------------
+def _lod_case(grid=48, n=600):
+    ls = synth.abc_lineset(n, 100, 21, perturb=True)
+    ref, _ = U.oracle_csr_from_xyz(ls, grid, 32)
+    s = L.lineset_voxelize(ls.curve_off, grid, 32, xyz=ls.xyz, attr=ls.attr)
+    return ls, ref, s
+
+
+def test_lod_pyramid_parity():
+    ls, ref, s = _lod_case()
+    lut = synth.lut_importance_alpha()
+    L.lineset_build_lod(s, U.dev(lut), opaque=False)
+    torch.cuda.synchronize()
+    cnt, ln, rho, dims, loff = O.lod(ref, 48, 32, lut, opaque=False)
+    for what, r in ((L.EXPORT_LOD_COUNT, cnt), (L.EXPORT_LOD_LEN, ln), (L.EXPORT_LOD_RHO, rho)):
+        g = L.lineset_export(s, what).cpu().numpy().astype(np.float64)
+        err = np.abs(g - r) / np.maximum(np.abs(r), 1e-30)
+        print(f"[lod {what}] max_rel_err={err.max():.3e}", flush=True)
+        assert np.allclose(g, r, rtol=1e-5, atol=1e-12)
+    assert s.info().n_levels == len(dims)
+
+
+def test_illumination_grids_parity():
+    ls, ref, s = _lod_case(grid=40, n=800)
+    lut = synth.lut_importance_alpha()
+    light = synth.LIGHT_DIR
+    L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, ao_cones=16, ao_radius=15.0,
+                        build_shadow=True, light_dir=light)
+    torch.cuda.synchronize()
+    _, _, rho, _, _ = O.lod(ref, 40, 32, lut, opaque=False)
+    ao = O.ao_grid(rho, 40, 16, 15.0, 1.0)
+    sh = O.shadow_grid(rho, 40, np.array(light, dtype=np.float32).astype(np.float64))
+    gao = L.lineset_export(s, L.EXPORT_AO).cpu().numpy()
+    gsh = L.lineset_export(s, L.EXPORT_SHADOW).cpu().numpy()
+    print(f"[illum] ao max_abs_err={np.abs(gao - ao).max():.3e} "
+          f"sh max_abs_err={np.abs(gsh - sh).max():.3e} ao_min={ao.min():.3f} sh_min={sh.min():.3f}",
+          flush=True)
+    assert ao.min() < 0.95 and sh.min() < 0.95
+    assert np.abs(gao - ao).max() < 1e-5
+    assert np.abs(gsh - sh).max() < 1e-5
