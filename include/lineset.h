@@ -197,7 +197,7 @@ int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_param
 /* Same image as lineset_render, with per-frame work counters (host struct,
  * filled after the call synchronises the stream). */
 typedef struct {
-  int64_t visited;          /* voxels stepped through */
+  int64_t visited;          /* voxels whose list header was read */
   int64_t nonempty;         /* visited voxels whose own list is not empty */
   int64_t tested;           /* ray-capsule tests */
   int64_t hits;             /* accepted hits */
@@ -205,6 +205,7 @@ typedef struct {
   int64_t list_bytes;       /* bytes of offsets and records read */
   int64_t sort_passes;      /* extra passes for voxels with more hits than the sort buffer */
   int64_t merge_evictions;  /* open intervals evicted from the bounded merge table */
+  int64_t macro_skips;      /* empty 4^3 macro cells jumped over */
 } ls_render_counters;
 
 int lineset_render_counted(ls_lineset_t set, const ls_camera* cam,

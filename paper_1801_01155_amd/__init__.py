@@ -54,7 +54,8 @@ class RenderParams(C.Structure):
 
 class RenderCounters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("visited", "nonempty", "tested", "hits", "fragments",
-                                          "list_bytes", "sort_passes", "merge_evictions")]
+                                          "list_bytes", "sort_passes", "merge_evictions",
+                                          "macro_skips")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

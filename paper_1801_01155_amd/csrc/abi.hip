@@ -355,6 +355,7 @@ int lineset_render_counted(ls_lineset_t s, const ls_camera* cam, const ls_render
   counters->list_bytes = (int64_t)h.list_bytes;
   counters->sort_passes = (int64_t)h.sort_passes;
   counters->merge_evictions = (int64_t)h.merge_evictions;
+  counters->macro_skips = (int64_t)h.macro_skips;
   return LS_OK;
 }
 

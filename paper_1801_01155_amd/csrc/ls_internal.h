@@ -92,7 +92,7 @@ int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_
 // Rendering (render.hip).
 struct RenderCounters {
   unsigned long long visited, nonempty, tested, hits, fragments, list_bytes, sort_passes,
-      merge_evictions;
+      merge_evictions, macro_skips;
 };
 
 int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,

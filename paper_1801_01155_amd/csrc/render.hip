@@ -34,7 +34,9 @@ constexpr int kXcds = 8;
 struct RenderArgs {
   const uint32_t* offsets;
   const uint64_t* records;
+  const unsigned long long* occ;  // 1 bit per 4^3 macro cell
   int32_t g[3];
+  int32_t mg[3];                  // macro grid dims
   float inv_bins;
   const float* lut;
   const float* ao;
@@ -52,7 +54,7 @@ struct RenderArgs {
 
 struct Counts {
   uint32_t visited = 0, nonempty = 0, tested = 0, hits = 0, fragments = 0, passes = 0,
-           evictions = 0;
+           evictions = 0, skips = 0;
   uint32_t list_bytes = 0;
 };
 
@@ -423,6 +425,59 @@ __device__ inline double peek_t1(const Ray& ray) {
   return m;
 }
 
+// Empty-space skipping. The fine walk handles plane crossings in
+// lexicographic (t, axis) order. Leaving an empty 4^3 macro cell M, it stops
+// at the first crossing of M's boundary, (T*, a*) = lexicographic minimum over
+// the axes of (t of the boundary plane, axis). Jumping there directly gives the
+// same state: on the exit axis the cell moves to the first cell past the
+// boundary; on every other axis the cell advances by the number of its planes
+// inside M with (t, axis) < (T*, a*) (at most 3, tested with the same fp64
+// formula); the next crossings are recomputed from the new cells. Voxel order
+// and t values of every non-empty voxel are therefore unchanged.
+__device__ inline void macro_jump(const RenderArgs& R, Ray& ray, const int32_t m[3]) {
+  double T[3];
+  int32_t B[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (ray.step[a] > 0) {
+      B[a] = min(4 * (m[a] + 1), R.g[a]);
+      T[a] = __dmul_rn(__dadd_rn((double)B[a], -ray.od[a]), ray.inv[a]);
+    } else if (ray.step[a] < 0) {
+      B[a] = 4 * m[a];
+      T[a] = __dmul_rn(__dadd_rn((double)B[a], -ray.od[a]), ray.inv[a]);
+    } else {
+      B[a] = 0;
+      T[a] = INFINITY;
+    }
+  }
+  int ax = 0;
+  if (T[1] < T[0]) ax = 1;
+  if (T[2] < (ax == 0 ? T[0] : T[1])) ax = 2;
+  const double Ts = ax == 0 ? T[0] : (ax == 1 ? T[1] : T[2]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (ray.step[b] == 0) continue;
+    int32_t c = ray.cell[b];
+    if (b == ax) {
+      c = ray.step[b] > 0 ? B[b] : B[b] - 1;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int32_t plane = ray.step[b] > 0 ? c + 1 : c;
+        if (plane == B[b]) break;
+        const double t = __dmul_rn(__dadd_rn((double)plane, -ray.od[b]), ray.inv[b]);
+        if (t < Ts || (t == Ts && b < ax)) c += ray.step[b];
+        else break;
+      }
+    }
+    ray.cell[b] = c;
+    const double plane = (double)(ray.step[b] > 0 ? c + 1 : c);
+    ray.tnext[b] = __dmul_rn(__dadd_rn(plane, -ray.od[b]), ray.inv[b]);
+  }
+  ray.t0 = Ts;
+  if (ray.cell[ax] < 0 || ray.cell[ax] >= R.g[ax]) ray.alive = false;
+}
+
 __device__ inline void local_origin(const Ray& ray, double t, const int32_t cell[3], float q[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) q[a] = (float)(fma(t, (double)ray.d[a], ray.od[a]) - (double)cell[a]);
@@ -585,10 +640,10 @@ __device__ inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Sh
 }
 
 __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
-  unsigned long long v[8] = {c.visited, c.nonempty, c.tested, c.hits, c.fragments, c.list_bytes,
-                             c.passes, c.evictions};
+  unsigned long long v[9] = {c.visited, c.nonempty, c.tested, c.hits, c.fragments, c.list_bytes,
+                             c.passes, c.evictions, c.skips};
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 9; ++k) {
     unsigned long long x = v[k];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
@@ -603,6 +658,7 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
     atomicAdd(&out->list_bytes, v[5]);
     atomicAdd(&out->sort_passes, v[6]);
     atomicAdd(&out->merge_evictions, v[7]);
+    atomicAdd(&out->macro_skips, v[8]);
   }
 }
 
@@ -631,7 +687,23 @@ __device__ inline void render_pixel(const RenderArgs& R, int i, int j, Counts& c
     // every step moves one cell monotonically along one axis: at most
     // gx + gy + gz steps (the cap only guards against malformed input)
     const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
+    int64_t last_mid = -1;
+    unsigned long long last_occ = 0;
     for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
+      if (kMode == 0) {
+        const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
+        const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
+        if (mid != last_mid) {
+          last_mid = mid;
+          last_occ = (R.occ[mid >> 6] >> (mid & 63)) & 1ull;
+          cnt.list_bytes += 8u;
+        }
+        if (!last_occ) {
+          cnt.skips++;
+          macro_jump(R, ray, m);
+          continue;
+        }
+      }
       cnt.visited++;
       if (kMode == 0) {
         const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
@@ -677,6 +749,8 @@ int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_para
   RenderArgs R{};
   R.offsets = s->offsets;
   R.records = s->records;
+  R.occ = reinterpret_cast<const unsigned long long*>(s->occupancy);
+  for (int a = 0; a < 3; ++a) R.mg[a] = s->macro[a];
   for (int a = 0; a < 3; ++a) {
     R.g[a] = s->grid[a];
     R.eye[a] = cam->eye[a];
