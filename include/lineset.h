@@ -213,6 +213,53 @@ int lineset_render_counted(ls_lineset_t set, const ls_camera* cam,
                            ls_render_counters* counters, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched rendering: many views of many resident line sets (uneven sizes,
+ * mixed modes) in ONE persistent launch. The screen tiles of all views form
+ * one list split into 8 queues (one per XCD); workgroups pop tiles from their
+ * XCD's queue and steal from the others. Each view's pixels are computed
+ * exactly as lineset_render computes them.
+ *   flags LS_BATCH_AUTOTUNE: time every tile shape (1x1 .. 4x1 waves of 8x8
+ *         pixels) and persistent grid size on this batch at creation and keep
+ *         the fastest (cached per batch signature for the process);
+ *   flags LS_BATCH_GRAPH: capture the launch in a hipGraph replayed by
+ *         lineset_batch_render.
+ * The batch borrows the views' sets, LUTs and outputs: they must outlive it.
+ * Creation renders the batch while autotuning (outputs are overwritten).
+ * Errors: LS_EINVAL for an invalid view (same rules as lineset_render) or
+ * n_views outside [1, 2^20]; LS_ENOMEM. */
+typedef struct {
+  ls_lineset_t set;
+  ls_camera cam;
+  ls_render_params params;
+  float* rgba_out;           /* device, float [height][width][4] */
+} ls_view;
+
+typedef struct ls_batch* ls_batch_t;
+
+enum { LS_BATCH_AUTOTUNE = 1, LS_BATCH_GRAPH = 2 };
+
+typedef struct {
+  int32_t waves_x, waves_y;  /* tile shape: waves_x x waves_y waves of 8 x 8 pixels */
+  int32_t blocks;            /* persistent workgroups */
+  int32_t n_tiles;
+  int32_t autotuned;         /* 0 default plan, 1 tuned now, 2 from the cache */
+  int32_t candidates;        /* plans timed */
+  float tuned_ms;            /* best candidate's time per launch */
+  int32_t graph;             /* replayed from a hipGraph */
+} ls_batch_config;
+
+int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, void* hip_stream,
+                         ls_batch_t* out);
+int lineset_batch_render(ls_batch_t batch, void* hip_stream);
+int lineset_batch_render_counted(ls_batch_t batch, ls_render_counters* counters,
+                                 void* hip_stream);
+int lineset_batch_config(ls_batch_t batch, ls_batch_config* out);
+void lineset_batch_destroy(ls_batch_t batch);   /* waits for the device */
+
+/* One-shot: create (default plan, no graph), render, synchronise, destroy. */
+int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
 /* Inspection. */
 typedef struct {
   int32_t grid[3];

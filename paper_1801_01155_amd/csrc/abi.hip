@@ -101,6 +101,47 @@ void ls_free_all(ls_lineset* s) {
   s->bytes = 0;
 }
 
+int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params* p,
+                 const float* out) {
+  if (!s || !c || !p || !out || !p->lut_rgba) {
+    ls_set_error("lineset_render: null set, camera, params, lut or output");
+    return LS_EINVAL;
+  }
+  if (c->width <= 0 || c->height <= 0 || (int64_t)c->width * c->height > (1ll << 31)) {
+    ls_set_error("lineset_render: image size must be positive and below 2^31 pixels");
+    return LS_EINVAL;
+  }
+  if (!finite3(c->eye) || !finite3(c->forward) || !finite3(c->right) || !finite3(c->up)) {
+    ls_set_error("lineset_render: non-finite camera");
+    return LS_EINVAL;
+  }
+  if (c->forward[0] == 0.f && c->forward[1] == 0.f && c->forward[2] == 0.f) {
+    ls_set_error("lineset_render: forward is zero");
+    return LS_EINVAL;
+  }
+  if (!(p->radius > 0.f) || !std::isfinite(p->radius) || (p->mode == 1 && !(p->radius < 1.f))) {
+    ls_set_error("lineset_render: radius must be > 0 (and < 1 voxel in mode 1)");
+    return LS_EINVAL;
+  }
+  if (p->mode != 0 && p->mode != 1) {
+    ls_set_error("lineset_render: mode must be 0 or 1");
+    return LS_EINVAL;
+  }
+  if (p->shading < 0 || p->shading > 2) {
+    ls_set_error("lineset_render: shading must be 0, 1 or 2");
+    return LS_EINVAL;
+  }
+  if (p->shading == 2 && (!s->ao || !s->sh)) {
+    ls_set_error("lineset_render: shading 2 needs the AO and shadow grids (lineset_build_lod)");
+    return LS_EINVAL;
+  }
+  if (!aligned16(out) || !aligned16(p->lut_rgba)) {
+    ls_set_error("lineset_render: rgba_out and lut_rgba must be 16-byte aligned");
+    return LS_EINVAL;
+  }
+  return LS_OK;
+}
+
 extern "C" {
 
 const char* ls_last_error(void) { return g_err; }
@@ -273,46 +314,6 @@ int lineset_build_lod(ls_lineset_t s, const ls_lod_desc* d, void* hip_stream) {
   return LS_OK;
 }
 
-static int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params* p,
-                        const float* out) {
-  if (!s || !c || !p || !out || !p->lut_rgba) {
-    ls_set_error("lineset_render: null set, camera, params, lut or output");
-    return LS_EINVAL;
-  }
-  if (c->width <= 0 || c->height <= 0 || (int64_t)c->width * c->height > (1ll << 31)) {
-    ls_set_error("lineset_render: image size must be positive and below 2^31 pixels");
-    return LS_EINVAL;
-  }
-  if (!finite3(c->eye) || !finite3(c->forward) || !finite3(c->right) || !finite3(c->up)) {
-    ls_set_error("lineset_render: non-finite camera");
-    return LS_EINVAL;
-  }
-  if (c->forward[0] == 0.f && c->forward[1] == 0.f && c->forward[2] == 0.f) {
-    ls_set_error("lineset_render: forward is zero");
-    return LS_EINVAL;
-  }
-  if (!(p->radius > 0.f) || !std::isfinite(p->radius) || (p->mode == 1 && !(p->radius < 1.f))) {
-    ls_set_error("lineset_render: radius must be > 0 (and < 1 voxel in mode 1)");
-    return LS_EINVAL;
-  }
-  if (p->mode != 0 && p->mode != 1) {
-    ls_set_error("lineset_render: mode must be 0 or 1");
-    return LS_EINVAL;
-  }
-  if (p->shading < 0 || p->shading > 2) {
-    ls_set_error("lineset_render: shading must be 0, 1 or 2");
-    return LS_EINVAL;
-  }
-  if (p->shading == 2 && (!s->ao || !s->sh)) {
-    ls_set_error("lineset_render: shading 2 needs the AO and shadow grids (lineset_build_lod)");
-    return LS_EINVAL;
-  }
-  if (!aligned16(out) || !aligned16(p->lut_rgba)) {
-    ls_set_error("lineset_render: rgba_out and lut_rgba must be 16-byte aligned");
-    return LS_EINVAL;
-  }
-  return LS_OK;
-}
 
 int lineset_render(ls_lineset_t s, const ls_camera* cam, const ls_render_params* p,
                    float* rgba_out, void* hip_stream) {

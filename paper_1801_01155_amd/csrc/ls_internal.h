@@ -95,5 +95,9 @@ struct RenderCounters {
       merge_evictions, macro_skips;
 };
 
+// Validates one view's camera / parameters / output (sets the error text).
+int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params* p,
+                 const float* out);
+
 int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
                  float* out, RenderCounters* dev_counters, hipStream_t st);

@@ -22,7 +22,7 @@
 //  5. per hit in order: per-curve interval merge in an 8-entry register
 //     table (the oldest interval is evicted when full), shading, premultiplied
 //     front-to-back compositing, termination at alpha_stop.
-#include "ls_internal.h"
+#include "render_args.h"
 
 namespace {
 
@@ -31,26 +31,7 @@ constexpr int kSortSlots = 8;
 constexpr int kMergeSlots = 8;
 constexpr int kXcds = 8;
 
-struct RenderArgs {
-  const uint32_t* offsets;
-  const uint64_t* records;
-  const unsigned long long* occ;  // 1 bit per 4^3 macro cell
-  int32_t g[3];
-  int32_t mg[3];                  // macro grid dims
-  float inv_bins;
-  const float* lut;
-  const float* ao;
-  const float* sh;
-  float eye[3], fwd[3], right[3], up[3];
-  int32_t ortho, W, H;
-  float radius, r2, alpha_stop;
-  int32_t opaque, merge, shading;
-  float ka, kd, ks, shin;
-  float light[3];
-  float* out;
-  RenderCounters* counters;
-  int32_t tiles_x, n_tiles, tiles_per_xcd;
-};
+
 
 struct Counts {
   uint32_t visited = 0, nonempty = 0, tested = 0, hits = 0, fragments = 0, passes = 0,
@@ -725,7 +706,19 @@ __device__ inline void render_pixel(const RenderArgs& R, int i, int j, Counts& c
   reinterpret_cast<float4*>(R.out)[(int64_t)j * R.W + i] = px;
 }
 
-template <int kMode, bool kCount>
+// Pixel of lane `lane` in wave `wave` of tile `tile` (tile = wx x wy waves of 8 x 8).
+__device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int lane, int& i, int& j) {
+  const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
+  i = tx * 8 * R.wx + (wave % R.wx) * 8 + (lane & 7);
+  j = ty * 8 * R.wy + (wave / R.wx) * 8 + (lane >> 3);
+}
+
+__device__ inline void render_any(const RenderArgs& R, int i, int j, Counts& cnt) {
+  if (R.mode == 0) render_pixel<0>(R, i, j, cnt);
+  else render_pixel<1>(R, i, j, cnt);
+}
+
+template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   // XCD-banded tile order: workgroup b runs on XCD b % 8; give each XCD a
   // contiguous run of tiles.
@@ -733,25 +726,71 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   const int tile = (b % kXcds) * R.tiles_per_xcd + b / kXcds;
   Counts cnt;
   if (tile < R.n_tiles) {
-    const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
-    if (i < R.W && j < R.H) render_pixel<kMode>(R, i, j, cnt);
+    int i, j;
+    tile_pixel(R, tile, threadIdx.x >> 6, threadIdx.x & 63, i, j);
+    if (i < R.W && j < R.H) render_any(R, i, j, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
 
+// Persistent batched renderer: one launch renders the tiles of many views.
+// The global tile list (views concatenated, tile_start = prefix of the
+// views' tile counts) is cut into 8 contiguous queues, one per XCD; a
+// workgroup pops tiles from its own XCD's queue and then steals from the
+// others. Every workgroup reaches the exit once all queues are drained.
+template <bool kCount>
+__global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __restrict__ views,
+                                                         const int32_t* __restrict__ tile_start,
+                                                         int32_t n_views, BatchQueues q,
+                                                         unsigned* __restrict__ counters) {
+  __shared__ int s_tile;
+  const int home = blockIdx.x % kXcds;
+  int qi = 0;
+  Counts cnt;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int t = -1;
+      while (qi < kXcds) {
+        const int qq = (home + qi) % kXcds;
+        const unsigned k = atomicAdd(counters + qq, 1u);
+        if (k < (unsigned)q.len[qq]) {
+          t = q.begin[qq] + (int)k;
+          break;
+        }
+        ++qi;
+      }
+      s_tile = t;
+    }
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();
+    if (t < 0) break;
+    // view owning tile t: last v with tile_start[v] <= t
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int v = __builtin_amdgcn_readfirstlane(lo);
+    const RenderArgs R = views[v];
+    int i, j;
+    tile_pixel(R, t - tile_start[v], threadIdx.x >> 6, threadIdx.x & 63, i, j);
+    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, i, j, cnt);
+  }
+  if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);
+}
+
 }  // namespace
 
-int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p, float* out,
-                 RenderCounters* dev_counters, hipStream_t st) {
+int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
+                     float* out, int wx, int wy, RenderCounters* dev_counters, RenderArgs* Rp) {
   RenderArgs R{};
   R.offsets = s->offsets;
   R.records = s->records;
   R.occ = reinterpret_cast<const unsigned long long*>(s->occupancy);
-  for (int a = 0; a < 3; ++a) R.mg[a] = s->macro[a];
   for (int a = 0; a < 3; ++a) {
+    R.mg[a] = s->macro[a];
     R.g[a] = s->grid[a];
     R.eye[a] = cam->eye[a];
     R.fwd[a] = cam->forward[a];
@@ -769,6 +808,7 @@ int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_para
   R.radius = p->radius;
   R.r2 = p->radius * p->radius;
   R.alpha_stop = p->alpha_stop;
+  R.mode = p->mode;
   R.opaque = p->opaque;
   R.merge = p->merge_curves;
   R.shading = p->shading;
@@ -778,19 +818,61 @@ int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_para
   R.shin = p->shininess;
   R.out = out;
   R.counters = dev_counters;
-  R.tiles_x = (R.W + 15) / 16;
-  const int tiles_y = (R.H + 15) / 16;
+  R.wx = wx;
+  R.wy = wy;
+  R.tiles_x = (R.W + 8 * wx - 1) / (8 * wx);
+  const int tiles_y = (R.H + 8 * wy - 1) / (8 * wy);
   R.n_tiles = R.tiles_x * tiles_y;
   R.tiles_per_xcd = (R.n_tiles + kXcds - 1) / kXcds;
+  *Rp = R;
+  return LS_OK;
+}
+
+int launch_render(const RenderArgs& R, hipStream_t st) {
   const unsigned blocks = (unsigned)(R.tiles_per_xcd * kXcds);
-  const bool count = dev_counters != nullptr;
-  if (p->mode == 0) {
-    if (count) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(kBlock), 0, st, R);
-    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(kBlock), 0, st, R);
-  } else {
-    if (count) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(kBlock), 0, st, R);
-    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(kBlock), 0, st, R);
-  }
+  const unsigned threads = (unsigned)(64 * R.wx * R.wy);
+  if (R.counters) hipLaunchKernelGGL((k_render<true>), dim3(blocks), dim3(threads), 0, st, R);
+  else hipLaunchKernelGGL((k_render<false>), dim3(blocks), dim3(threads), 0, st, R);
   LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p, float* out,
+                 RenderCounters* dev_counters, hipStream_t st) {
+  RenderArgs R;
+  make_render_args(s, cam, p, out, 2, 2, dev_counters, &R);
+  return launch_render(R, st);
+}
+
+BatchQueues make_queues(int total_tiles) {
+  BatchQueues q{};
+  for (int k = 0; k < kXcds; ++k) {
+    const int b = (int)((int64_t)total_tiles * k / kXcds);
+    const int e = (int)((int64_t)total_tiles * (k + 1) / kXcds);
+    q.begin[k] = b;
+    q.len[k] = e - b;
+  }
+  return q;
+}
+
+int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_start, int n_views,
+                        const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
+                        bool count, hipStream_t st) {
+  const unsigned threads = (unsigned)(64 * plan.wx * plan.wy);
+  if (count)
+    hipLaunchKernelGGL((k_render_batch<true>), dim3(plan.blocks), dim3(threads), 0, st, dev_views,
+                       dev_tile_start, n_views, q, dev_queue);
+  else
+    hipLaunchKernelGGL((k_render_batch<false>), dim3(plan.blocks), dim3(threads), 0, st, dev_views,
+                       dev_tile_start, n_views, q, dev_queue);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+int batch_blocks_per_cu(int wx, int wy, int* out) {
+  int n = 0;
+  LS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_render_batch<false>,
+                                                      64 * wx * wy, 0));
+  *out = n > 0 ? n : 1;
   return LS_OK;
 }

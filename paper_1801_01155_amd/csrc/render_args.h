@@ -1,0 +1,50 @@
+// Per-view render descriptor shared by the plain, batched and served paths.
+#pragma once
+
+#include "ls_internal.h"
+
+// Everything one view needs, passed by value to the plain kernel and read
+// from device memory (uniform, scalar loads) by the persistent kernel.
+struct RenderArgs {
+  const uint32_t* offsets;
+  const uint64_t* records;
+  const unsigned long long* occ;  // 1 bit per 4^3 macro cell
+  int32_t g[3];
+  int32_t mg[3];                  // macro grid dims
+  float inv_bins;
+  const float* lut;
+  const float* ao;
+  const float* sh;
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t ortho, W, H;
+  float radius, r2, alpha_stop;
+  int32_t mode, opaque, merge, shading;
+  float ka, kd, ks, shin;
+  float light[3];
+  float* out;
+  RenderCounters* counters;
+  int32_t wx, wy;                 // tile = wx x wy waves of 8 x 8 pixels
+  int32_t tiles_x, n_tiles, tiles_per_xcd;
+};
+
+// Tile queues of the persistent kernel: one contiguous range per XCD.
+struct BatchQueues {
+  int32_t begin[8];
+  int32_t len[8];
+};
+
+struct BatchPlan {
+  int32_t wx, wy;     // tile shape in waves
+  int32_t blocks;     // persistent workgroups
+};
+
+int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
+                     float* out, int wx, int wy, RenderCounters* dev_counters, RenderArgs* R);
+int launch_render(const RenderArgs& R, hipStream_t st);
+BatchQueues make_queues(int total_tiles);
+// dev_queue: 8 queue counters (zeroed before the launch), followed by a
+// RenderCounters block when `count` is set.
+int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_start, int n_views,
+                        const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
+                        bool count, hipStream_t st);
+int batch_blocks_per_cu(int wx, int wy, int* out);
