@@ -282,3 +282,91 @@ def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
     _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
                                 _stream(stream)))
     return t[:n]
+
+
+# ---------------------------------------------------------------------------
+# Batched rendering
+
+BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
+
+
+class ViewS(C.Structure):
+    _fields_ = [("set", C.c_void_p), ("cam", CameraS), ("params", RenderParams),
+                ("rgba_out", C.c_void_p)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("waves_x", C.c_int32), ("waves_y", C.c_int32), ("blocks", C.c_int32),
+                ("n_tiles", C.c_int32), ("autotuned", C.c_int32), ("candidates", C.c_int32),
+                ("tuned_ms", C.c_float), ("graph", C.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _bind_batch(L):
+    if getattr(L, "_batch_bound", False):
+        return
+    L.lineset_batch_create.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_int32, C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+    L.lineset_batch_render.argtypes = [C.c_void_p, C.c_void_p]
+    L.lineset_batch_render_counted.argtypes = [C.c_void_p, C.POINTER(RenderCounters), C.c_void_p]
+    L.lineset_batch_config.argtypes = [C.c_void_p, C.POINTER(BatchConfig)]
+    L.lineset_batch_destroy.argtypes = [C.c_void_p]
+    L.lineset_batch_destroy.restype = None
+    L.lineset_render_batch.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_void_p]
+    L._batch_bound = True
+
+
+def make_views(items):
+    """items: sequence of (LineSet, camera, lut_tensor, out_tensor, params dict)."""
+    arr = (ViewS * len(items))()
+    for k, (ls, cam, lut, out, params) in enumerate(items):
+        arr[k].set = ls.handle.value
+        arr[k].cam = camera_struct(cam)
+        arr[k].params = render_params(lut, **params)
+        arr[k].rgba_out = out.data_ptr()
+    return arr
+
+
+class Batch:
+    """Owns an ls_batch_t (one persistent launch over many views)."""
+
+    def __init__(self, items, autotune=False, graph=False, stream=None):
+        L = lib()
+        _bind_batch(L)
+        self._items = list(items)      # keep sets, LUTs and outputs alive
+        self._views = make_views(self._items)
+        flags = (BATCH_AUTOTUNE if autotune else 0) | (BATCH_GRAPH if graph else 0)
+        h = C.c_void_p()
+        _check(L.lineset_batch_create(self._views, len(self._items), flags, _stream(stream),
+                                      C.byref(h)))
+        self.handle = h
+
+    def render(self, stream=None):
+        _check(lib().lineset_batch_render(self.handle, _stream(stream)))
+
+    def render_counted(self, stream=None):
+        k = RenderCounters()
+        _check(lib().lineset_batch_render_counted(self.handle, C.byref(k), _stream(stream)))
+        return k.as_dict()
+
+    def config(self):
+        c = BatchConfig()
+        _check(lib().lineset_batch_config(self.handle, C.byref(c)))
+        return c.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.lineset_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def lineset_render_batch(items, stream=None):
+    L = lib()
+    _bind_batch(L)
+    views = make_views(items)
+    _check(L.lineset_render_batch(views, len(items), _stream(stream)))

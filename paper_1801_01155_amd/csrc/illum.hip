@@ -7,8 +7,8 @@
 // min(L, floor(log2 D)) (cell-centred trilinear, clamp to edge); each adds
 // rho * D to the occlusion, then s += D, while s < s_max and the point is
 // inside the grid; occlusion saturates at 1. Sample positions and lattice
-// coordinates are formed in fp64 (they reach hundreds of voxels along the
-// shadow cone), weights and accumulation in fp32. One thread per voxel; the
+// inside-the-grid tests are made in fp64; lattice coordinates and weights in
+// fp32 relative to the voxel, accumulation in fp32. One thread per voxel; the
 // pyramid levels are small enough past level 2 to stay in L2.
 #include "ls_internal.h"
 
@@ -34,54 +34,73 @@ struct Cones {
   double dir[kMaxCones][3];
 };
 
-__device__ inline float sample(const Pyramid& P, int lv, const double x[3]) {
-  const double scale = ldexp(1.0, -lv);
+// Trilinear sample of level `lv` at the point v + f (v the voxel corner,
+// integer; f a local offset in voxel units). The level coordinate is formed
+// from v's low bits and f in fp32, so it keeps ~1e-7 cell precision at every
+// level. The two x-neighbour taps are one 8-byte load: the pair starts at
+// j = clamp(i0, 0, D - 2) and the x weight is clamp(x - j, 0, 1), which is
+// clamp-to-edge interpolation.
+__device__ inline float sample(const Pyramid& P, int lv, const int32_t v[3], const float f[3]) {
+  const float scale = __builtin_ldexpf(1.0f, -lv);
+  const int32_t mask = (1 << lv) - 1;
   const int32_t* dm = P.dims[lv];
-  int32_t i0[3], i1[3];
-  float f[3];
+  int32_t i0[3];
+  float fr[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double g = x[a] * scale - 0.5;
-    double fl = floor(g);
-    f[a] = (float)(g - fl);
-    int32_t lo = (int32_t)fl;
-    int32_t hi = lo + 1;
-    lo = lo < 0 ? 0 : (lo > dm[a] - 1 ? dm[a] - 1 : lo);
-    hi = hi < 0 ? 0 : (hi > dm[a] - 1 ? dm[a] - 1 : hi);
-    i0[a] = lo;
-    i1[a] = hi;
+    const float x = ((float)(v[a] & mask) + f[a]) * scale - 0.5f;
+    const float fl = floorf(x);
+    fr[a] = x - fl;
+    i0[a] = (v[a] >> lv) + (int32_t)fl;
   }
   const float* r = P.rho + P.off[lv];
   const int64_t sy = dm[0], sz = (int64_t)dm[0] * dm[1];
-  const int64_t z0 = i0[2] * sz, z1 = i1[2] * sz, y0 = i0[1] * sy, y1 = i1[1] * sy;
-  float c00 = r[i0[0] + y0 + z0] * (1.f - f[0]) + r[i1[0] + y0 + z0] * f[0];
-  float c10 = r[i0[0] + y1 + z0] * (1.f - f[0]) + r[i1[0] + y1 + z0] * f[0];
-  float c01 = r[i0[0] + y0 + z1] * (1.f - f[0]) + r[i1[0] + y0 + z1] * f[0];
-  float c11 = r[i0[0] + y1 + z1] * (1.f - f[0]) + r[i1[0] + y1 + z1] * f[0];
-  float c0 = c00 * (1.f - f[1]) + c10 * f[1];
-  float c1 = c01 * (1.f - f[1]) + c11 * f[1];
-  return c0 * (1.f - f[2]) + c1 * f[2];
+  const int32_t y0 = min(max(i0[1], 0), dm[1] - 1), y1 = min(max(i0[1] + 1, 0), dm[1] - 1);
+  const int32_t z0 = min(max(i0[2], 0), dm[2] - 1), z1 = min(max(i0[2] + 1, 0), dm[2] - 1);
+  float c[4];
+  const int64_t rows[4] = {y0 * sy + z0 * sz, y1 * sy + z0 * sz, y0 * sy + z1 * sz, y1 * sy + z1 * sz};
+  if (dm[0] >= 2) {
+    const int32_t j = min(max(i0[0], 0), dm[0] - 2);
+    const float wx = fminf(fmaxf((float)(i0[0] - j) + fr[0], 0.f), 1.f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float2 pr;
+      __builtin_memcpy(&pr, r + rows[k] + j, sizeof(pr));
+      c[k] = pr.x + wx * (pr.y - pr.x);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = r[rows[k]];
+  }
+  const float c0 = c[0] * (1.f - fr[1]) + c[1] * fr[1];
+  const float c1 = c[2] * (1.f - fr[1]) + c[3] * fr[1];
+  return c0 * (1.f - fr[2]) + c1 * fr[2];
 }
 
-__device__ inline float cone(const Pyramid& P, const double p[3], const double u[3], double s_max,
-                             double aperture) {
+// Occlusion along one cone from the centre of voxel v. The inside-the-grid
+// test is made in fp64 on p + s u (the same expression as the definition);
+// the sample itself uses the local offset f = 0.5 + s u in fp32.
+__device__ inline float cone(const Pyramid& P, const int32_t v[3], const double u[3],
+                             double s_max, double aperture) {
   const int top = P.n_levels - 1;
+  const float u32[3] = {(float)u[0], (float)u[1], (float)u[2]};
   float occ = 0.f;
   double s = 1.0;
   while (s < s_max) {
-    double x[3];
     bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      x[a] = p[a] + s * u[a];
-      inside &= x[a] >= 0.0 && x[a] < (double)P.g[a];
+      const double x = ((double)v[a] + 0.5) + s * u[a];
+      inside &= x >= 0.0 && x < (double)P.g[a];
     }
     if (!inside) break;
     double D = aperture * s;
     D = D < 1.0 ? 1.0 : D;
     int lv = ilogb(D);
     lv = lv > top ? top : lv;
-    occ += sample(P, lv, x) * (float)D;
+    const float sf = (float)s;
+    const float f[3] = {0.5f + sf * u32[0], 0.5f + sf * u32[1], 0.5f + sf * u32[2]};
+    occ += sample(P, lv, v, f) * (float)D;
     if (occ >= 1.f) break;
     s += D;
   }
@@ -91,8 +110,8 @@ __device__ inline float cone(const Pyramid& P, const double p[3], const double u
 __global__ __launch_bounds__(kBlock) void k_ao(Pyramid P, Cones C, int64_t nvox, float* ao) {
   int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (v >= nvox) return;
-  const double p[3] = {(double)(v % P.g[0]) + 0.5, (double)((v / P.g[0]) % P.g[1]) + 0.5,
-                       (double)(v / ((int64_t)P.g[0] * P.g[1])) + 0.5};
+  const int32_t p[3] = {(int32_t)(v % P.g[0]), (int32_t)((v / P.g[0]) % P.g[1]),
+                        (int32_t)(v / ((int64_t)P.g[0] * P.g[1]))};
   float sum = 0.f;
   for (int c = 0; c < C.n; ++c) sum += cone(P, p, C.dir[c], C.s_max, C.aperture);
   ao[v] = 1.f - sum / (float)C.n;
@@ -101,8 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_ao(Pyramid P, Cones C, int64_t nvox,
 __global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, int64_t nvox, float* sh) {
   int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (v >= nvox) return;
-  const double p[3] = {(double)(v % P.g[0]) + 0.5, (double)((v / P.g[0]) % P.g[1]) + 0.5,
-                       (double)(v / ((int64_t)P.g[0] * P.g[1])) + 0.5};
+  const int32_t p[3] = {(int32_t)(v % P.g[0]), (int32_t)((v / P.g[0]) % P.g[1]),
+                        (int32_t)(v / ((int64_t)P.g[0] * P.g[1]))};
   sh[v] = 1.f - cone(P, p, C.dir[0], INFINITY, C.aperture);
 }
 

@@ -22,6 +22,7 @@
 // arithmetic on the 1/256-voxel lattice.
 #include "ls_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -260,21 +261,37 @@ __global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint
   records[lo + r] = rec[e];
 }
 
+// Non-empty voxel count and longest list: grid-stride loop, wave and block
+// reduction, one atomic per workgroup.
 __global__ __launch_bounds__(kBlock) void k_list_stats(const uint32_t* offsets, int64_t nvox,
                                                        unsigned long long* nonempty,
                                                        unsigned int* max_list) {
-  int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  unsigned n = 0;
-  if (v < nvox) n = offsets[v + 1] - offsets[v];
-  unsigned long long ne = n > 0;
-  unsigned mx = n;
+  __shared__ unsigned long long s_ne[kBlock / 64];
+  __shared__ unsigned s_mx[kBlock / 64];
+  unsigned long long ne = 0;
+  unsigned mx = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * kBlock) {
+    const unsigned n = offsets[v + 1] - offsets[v];
+    ne += n > 0;
+    mx = n > mx ? n : mx;
+  }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     ne += __shfl_xor(ne, d, 64);
-    unsigned o = __shfl_xor(mx, d, 64);
+    const unsigned o = __shfl_xor(mx, d, 64);
     mx = o > mx ? o : mx;
   }
   if ((threadIdx.x & 63) == 0) {
+    s_ne[threadIdx.x >> 6] = ne;
+    s_mx[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      ne += s_ne[w];
+      mx = s_mx[w] > mx ? s_mx[w] : mx;
+    }
     if (ne) atomicAdd(nonempty, ne);
     if (mx) atomicMax(max_list, mx);
   }
@@ -527,7 +544,8 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   DeviceBuf stats;
   if ((rc = stats.alloc(16))) return rc;
   LS_HIP(hipMemsetAsync(stats.p, 0, 16, st));
-  hipLaunchKernelGGL(k_list_stats, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, s->offsets,
+  const unsigned stat_blocks = std::min<unsigned>(blocks_for(s->nvox), 2048u);
+  hipLaunchKernelGGL(k_list_stats, dim3(stat_blocks), dim3(kBlock), 0, st, s->offsets,
                      s->nvox, stats.as<unsigned long long>(),
                      (unsigned int*)(stats.as<char>() + 8));
   LS_HIP(hipGetLastError());
