@@ -260,6 +260,55 @@ void lineset_batch_destroy(ls_batch_t batch);   /* waits for the device */
 int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Render server: keeps voxelized line sets resident, admits render requests
+ * by an HBM budget and batches them continuously. A scheduler thread owns
+ * n_slots launch slots (stream + event + descriptor buffers, allocated at
+ * creation; nothing is allocated afterwards). Whenever a slot is free it
+ * takes the queue's head requests, in arrival order, while their
+ * reservations (W*H*16 bytes of output plus a descriptor) fit into
+ * budget - resident sets - requests in flight, and renders them in one
+ * batched launch; requests arriving meanwhile go into the next free slot, so
+ * batches overlap on the device. Each request's image equals its
+ * lineset_render image.
+ *   ls_server_add_lineset: the set's device bytes count against the budget
+ *     (LS_ENOMEM if they do not fit); the server borrows the set.
+ *   ls_server_submit: non-blocking; LS_EBUSY when max_queue requests wait,
+ *     LS_ENOMEM when the request alone exceeds what the budget leaves,
+ *     LS_EINVAL for invalid views (lineset_render's rules). rgba_out and the
+ *     LUT must stay valid until the request completes.
+ *   ls_server_wait: blocks up to timeout_us (negative: forever); LS_OK once
+ *     the image is written (the ticket is then retired), LS_ETIMEOUT else.
+ *   ls_server_stats: latency percentiles from submission to observed
+ *     completion over all completed requests; Mrays/s over the span from the
+ *     first submission to the last completion. */
+typedef struct ls_server* ls_server_t;
+
+typedef struct {
+  size_t hbm_budget_bytes;
+  int32_t n_slots;           /* concurrent batched launches, 1..16 */
+  int32_t max_batch_views;   /* requests per launch, 1..4096 */
+  int32_t max_queue;         /* waiting requests before LS_EBUSY */
+} ls_server_config;
+
+typedef struct {
+  int64_t completed;
+  double p50_ms, p99_ms, max_ms;
+  double mrays_per_s;
+  int64_t batches;
+  double mean_batch;
+  int64_t queued, max_queue_depth, rejected;
+  size_t resident_bytes, inflight_bytes;
+} ls_server_report;
+
+int ls_server_create(const ls_server_config* cfg, ls_server_t* out);
+int ls_server_add_lineset(ls_server_t server, ls_lineset_t set, int32_t* set_id);
+int ls_server_submit(ls_server_t server, int32_t set_id, const ls_camera* cam,
+                     const ls_render_params* params, float* rgba_out, uint64_t* ticket);
+int ls_server_wait(ls_server_t server, uint64_t ticket, int64_t timeout_us);
+int ls_server_stats(ls_server_t server, ls_server_report* out);
+void ls_server_destroy(ls_server_t server);   /* finishes queued work first */
+
+/* ------------------------------------------------------------------------ */
 /* Inspection. */
 typedef struct {
   int32_t grid[3];

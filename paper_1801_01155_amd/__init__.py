@@ -370,3 +370,88 @@ def lineset_render_batch(items, stream=None):
     _bind_batch(L)
     views = make_views(items)
     _check(L.lineset_render_batch(views, len(items), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Render server
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("n_slots", C.c_int32),
+                ("max_batch_views", C.c_int32), ("max_queue", C.c_int32)]
+
+
+class ServerReport(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("mrays_per_s", C.c_double), ("batches", C.c_int64),
+                ("mean_batch", C.c_double), ("queued", C.c_int64), ("max_queue_depth", C.c_int64),
+                ("rejected", C.c_int64), ("resident_bytes", C.c_size_t),
+                ("inflight_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _bind_server(L):
+    if getattr(L, "_server_bound", False):
+        return
+    L.ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
+    L.ls_server_add_lineset.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+    L.ls_server_submit.argtypes = [C.c_void_p, C.c_int32, C.POINTER(CameraS),
+                                   C.POINTER(RenderParams), C.c_void_p, C.POINTER(C.c_uint64)]
+    L.ls_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64]
+    L.ls_server_stats.argtypes = [C.c_void_p, C.POINTER(ServerReport)]
+    L.ls_server_destroy.argtypes = [C.c_void_p]
+    L.ls_server_destroy.restype = None
+    L._server_bound = True
+
+
+class Server:
+    """Owns an ls_server_t. Keeps the sets, LUTs and outputs of pending
+    requests alive until they are waited for."""
+
+    def __init__(self, hbm_budget_bytes, n_slots=2, max_batch_views=64, max_queue=4096):
+        L = lib()
+        _bind_server(L)
+        cfg = ServerConfig(hbm_budget_bytes, n_slots, max_batch_views, max_queue)
+        h = C.c_void_p()
+        _check(L.ls_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._sets = []
+        self._pending = {}
+
+    def add_lineset(self, ls: LineSet) -> int:
+        sid = C.c_int32()
+        _check(lib().ls_server_add_lineset(self.handle, ls.handle, C.byref(sid)))
+        self._sets.append(ls)
+        return sid.value
+
+    def submit(self, set_id, cam, lut, out, **params) -> int:
+        c = camera_struct(cam)
+        p = render_params(lut, **params)
+        t = C.c_uint64()
+        _check(lib().ls_server_submit(self.handle, set_id, C.byref(c), C.byref(p),
+                                      C.c_void_p(out.data_ptr()), C.byref(t)))
+        self._pending[t.value] = (lut, out)
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        rc = lib().ls_server_wait(self.handle, C.c_uint64(ticket), C.c_int64(timeout_us))
+        if rc == LS_ETIMEOUT:
+            return False
+        _check(rc)
+        self._pending.pop(ticket, None)
+        return True
+
+    def stats(self):
+        r = ServerReport()
+        _check(lib().ls_server_stats(self.handle, C.byref(r)))
+        return r.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.ls_server_destroy(self.handle)
+        self.handle = None
+        self._pending = {}
+
+    def __del__(self):
+        self.close()

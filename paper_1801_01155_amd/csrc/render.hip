@@ -27,7 +27,7 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSortSlots = 8;
+constexpr int kSortSlots = 4;
 constexpr int kMergeSlots = 8;
 constexpr int kXcds = 8;
 
@@ -212,7 +212,7 @@ struct Shade {
 
 // Shade and composite one fragment. p is the entry point in the frame of
 // `cell`, a/b the record's endpoints in the same frame.
-__device__ inline void composite(const RenderArgs& R, const Shade& S, Accum& acc, uint64_t rec,
+__device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const Shade& S, Accum& acc, uint64_t rec,
                                  const int32_t cell[3], const float p[3], const float a[3],
                                  const float b[3], Counts& cnt) {
   const int attr = (int)((rec >> 32) & 0xFF);
@@ -265,6 +265,7 @@ struct HitBuf {
   float so[kSortSlots];
   uint32_t idx[kSortSlots];
   uint32_t aux[kSortSlots];
+  uint64_t rec[kSortSlots];
   int n = 0;
   int dropped = 0;
 
@@ -272,7 +273,7 @@ struct HitBuf {
     return ta < tb || (ta == tb && ia < ib);
   }
 
-  __device__ inline void insert(TKey tk, float sout, uint32_t id, uint32_t ax) {
+  __device__ inline void insert(TKey tk, float sout, uint32_t id, uint32_t ax, uint64_t rc) {
     if (n == kSortSlots && !less(tk, id, t[kSortSlots - 1], idx[kSortSlots - 1])) {
       ++dropped;
       return;
@@ -287,18 +288,34 @@ struct HitBuf {
         TKey t2 = t[i];
         float s2 = so[i];
         uint32_t i2 = idx[i], a2 = aux[i];
+        uint64_t r2 = rec[i];
         t[i] = tk;
         so[i] = sout;
         idx[i] = id;
         aux[i] = ax;
+        rec[i] = rc;
         tk = t2;
         sout = s2;
         id = i2;
         ax = a2;
+        rc = r2;
         if (!occupied) break;
       }
     }
     if (n < kSortSlots) ++n;
+  }
+
+  // Removes the smallest entry (slot 0), shifting the others down.
+  __device__ inline void pop_front() {
+#pragma unroll
+    for (int i = 0; i + 1 < kSortSlots; ++i) {
+      t[i] = t[i + 1];
+      so[i] = so[i + 1];
+      idx[i] = idx[i + 1];
+      aux[i] = aux[i + 1];
+      rec[i] = rec[i + 1];
+    }
+    --n;
   }
 };
 
@@ -456,7 +473,10 @@ __device__ inline void macro_jump(const RenderArgs& R, Ray& ray, const int32_t m
     ray.tnext[b] = __dmul_rn(__dadd_rn(plane, -ray.od[b]), ray.inv[b]);
   }
   ray.t0 = Ts;
-  if (ray.cell[ax] < 0 || ray.cell[ax] >= R.g[ax]) ray.alive = false;
+  // (selects rather than an indexed access keep the arrays in registers)
+  const int32_t ce = ax == 0 ? ray.cell[0] : (ax == 1 ? ray.cell[1] : ray.cell[2]);
+  const int32_t ge = ax == 0 ? R.g[0] : (ax == 1 ? R.g[1] : R.g[2]);
+  if (ce < 0 || ce >= ge) ray.alive = false;
 }
 
 __device__ inline void local_origin(const Ray& ray, double t, const int32_t cell[3], float q[3]) {
@@ -466,7 +486,7 @@ __device__ inline void local_origin(const Ray& ray, double t, const int32_t cell
 
 // Own-list mode: test the voxel's lines, accept t >= 0, composite in
 // (t, index) order.
-__device__ inline void voxel_fast(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+__device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
                                   float inv_dd, uint32_t lo, uint32_t hi, Accum& acc,
                                   Counts& cnt) {
   float q[3];
@@ -518,28 +538,29 @@ __device__ inline void voxel_fast(const RenderArgs& R, const Ray& ray, const Sha
       if (!(ray.t0 + (double)si >= 0.0)) continue;
       if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
       if (first) cnt.hits++;
-      buf.insert(si, so, k, 0u);
+      buf.insert(si, so, k, 0u, rec);
     }
     cnt.list_bytes += 8u * (hi - lo);
-#pragma unroll
-    for (int m = 0; m < kSortSlots; ++m) {
-      if (m >= buf.n || acc.done) break;
-      const uint64_t rec = R.records[buf.idx[m]];
+    // the pass's last key bounds the next pass (read before consuming)
+    last_t = buf.t[kSortSlots - 1];
+    last_i = buf.idx[kSortSlots - 1];
+    const bool more = buf.dropped != 0;
+    while (buf.n > 0 && !acc.done) {
+      const float t_in = buf.t[0], t_out = buf.so[0];
+      const uint64_t rec = buf.rec[0];
+      buf.pop_front();
       if (R.merge) {
         const uint32_t tag = (uint32_t)(rec >> 40);
-        if (merge_hit(acc, tag, ray.t0 + (double)buf.t[m], ray.t0 + (double)buf.so[m], cnt))
-          continue;
+        if (merge_hit(acc, tag, ray.t0 + (double)t_in, ray.t0 + (double)t_out, cnt)) continue;
       }
       float a[3], b[3], p[3];
       decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) p[c] = q[c] + buf.t[m] * ray.d[c];
+      for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
       composite(R, S, acc, rec, ray.cell, p, a, b, cnt);
     }
-    if (acc.done || buf.dropped == 0) break;
-    last_t = buf.t[kSortSlots - 1];
-    last_i = buf.idx[kSortSlots - 1];
+    if (acc.done || !more) break;
     first = false;
     cnt.passes++;
   }
@@ -557,7 +578,7 @@ __device__ inline double owner_ref(const Ray& ray, const int32_t w[3], double id
   return s * idd;
 }
 
-__device__ inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+__device__ __attribute__((always_inline)) inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
                                    float inv_dd, double idd, double t1, Accum& acc, Counts& cnt) {
   double last_t = -INFINITY;
   uint32_t last_i = 0;
@@ -587,24 +608,28 @@ __device__ inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Sh
         if (!(ti >= ray.t0 && ti < t1)) continue;
         if (!first && !HitBuf<double>::less(last_t, last_i, ti, k)) continue;
         if (first) cnt.hits++;
-        buf.insert(ti, (float)(tr + (double)so - ti), k, (uint32_t)nb);
+        buf.insert(ti, (float)(tr + (double)so - ti), k, (uint32_t)nb, rec);
       }
     }
-#pragma unroll
-    for (int m = 0; m < kSortSlots; ++m) {
-      if (m >= buf.n || acc.done) break;
-      const uint64_t rec = R.records[buf.idx[m]];
+    last_t = buf.t[kSortSlots - 1];
+    last_i = buf.idx[kSortSlots - 1];
+    const bool more = buf.dropped != 0;
+    while (buf.n > 0 && !acc.done) {
+      const double t_in = buf.t[0];
+      const float len = buf.so[0];
+      const int nb = (int)buf.aux[0];
+      const uint64_t rec = buf.rec[0];
+      buf.pop_front();
       if (!R.opaque && R.merge) {
         const uint32_t tag = (uint32_t)(rec >> 40);
-        if (merge_hit(acc, tag, buf.t[m], buf.t[m] + (double)buf.so[m], cnt)) continue;
+        if (merge_hit(acc, tag, t_in, t_in + (double)len, cnt)) continue;
       }
-      const int nb = (int)buf.aux[m];
       int32_t w[3] = {ray.cell[0] + nb % 3 - 1, ray.cell[1] + (nb / 3) % 3 - 1,
                       ray.cell[2] + nb / 9 - 1};
       const double tr = owner_ref(ray, w, idd);
       float q[3], a[3], b[3], p[3];
       local_origin(ray, tr, w, q);
-      const float s_in = (float)(buf.t[m] - tr);
+      const float s_in = (float)(t_in - tr);
       decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
@@ -612,9 +637,7 @@ __device__ inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Sh
       composite(R, S, acc, rec, w, p, a, b, cnt);
       if (R.opaque) acc.done = true;
     }
-    if (acc.done || buf.dropped == 0) break;
-    last_t = buf.t[kSortSlots - 1];
-    last_i = buf.idx[kSortSlots - 1];
+    if (acc.done || !more) break;
     first = false;
     cnt.passes++;
   }
@@ -644,7 +667,7 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
 }
 
 template <int kMode>
-__device__ inline void render_pixel(const RenderArgs& R, int i, int j, Counts& cnt) {
+__device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, int i, int j, Counts& cnt) {
   Ray ray;
   make_ray(R, i, j, ray.o, ray.d);
   dda_init(R, ray);
@@ -713,22 +736,25 @@ __device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int l
   j = ty * 8 * R.wy + (wave / R.wx) * 8 + (lane >> 3);
 }
 
-__device__ inline void render_any(const RenderArgs& R, int i, int j, Counts& cnt) {
+__device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, int i, int j, Counts& cnt) {
   if (R.mode == 0) render_pixel<0>(R, i, j, cnt);
   else render_pixel<1>(R, i, j, cnt);
 }
 
-template <bool kCount>
+template <int kMode, bool kCount>
 __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
-  // XCD-banded tile order: workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous run of tiles.
+  // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
+  // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every XCD
+  // gets a share of the part of the screen the grid covers.
   const int b = blockIdx.x;
-  const int tile = (b % kXcds) * R.tiles_per_xcd + b / kXcds;
+  const int x = b % kXcds, l = b / kXcds;
+  const int row = x + kXcds * (l / R.tiles_x);
+  const int tile = row * R.tiles_x + l % R.tiles_x;
   Counts cnt;
-  if (tile < R.n_tiles) {
+  if (row * R.tiles_x < R.n_tiles) {
     int i, j;
     tile_pixel(R, tile, threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if (i < R.W && j < R.H) render_any(R, i, j, cnt);
+    if (i < R.W && j < R.H) render_pixel<kMode>(R, i, j, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
@@ -752,9 +778,16 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
       int t = -1;
       while (qi < kXcds) {
         const int qq = (home + qi) % kXcds;
+        int qb = 0, ql = 0;
+#pragma unroll
+        for (int x = 0; x < kXcds; ++x)
+          if (x == qq) {
+            qb = q.begin[x];
+            ql = q.len[x];
+          }
         const unsigned k = atomicAdd(counters + qq, 1u);
-        if (k < (unsigned)q.len[qq]) {
-          t = q.begin[qq] + (int)k;
+        if (k < (unsigned)ql) {
+          t = qb + (int)k;
           break;
         }
         ++qi;
@@ -829,10 +862,16 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
 }
 
 int launch_render(const RenderArgs& R, hipStream_t st) {
-  const unsigned blocks = (unsigned)(R.tiles_per_xcd * kXcds);
+  const int tiles_y = R.n_tiles / R.tiles_x;
+  const unsigned blocks = (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
   const unsigned threads = (unsigned)(64 * R.wx * R.wy);
-  if (R.counters) hipLaunchKernelGGL((k_render<true>), dim3(blocks), dim3(threads), 0, st, R);
-  else hipLaunchKernelGGL((k_render<false>), dim3(blocks), dim3(threads), 0, st, R);
+  if (R.mode == 0) {
+    if (R.counters) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(threads), 0, st, R);
+    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(threads), 0, st, R);
+  } else {
+    if (R.counters) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(threads), 0, st, R);
+    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(threads), 0, st, R);
+  }
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
