@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched / served comparison")
     ap.add_argument("--cpu-sample-rows", type=int, default=8,
                     help="oracle renders every k-th image row")
     return ap.parse_args()
@@ -80,6 +82,120 @@ def cpu_baseline(ls, w, cam, lut, light, row_stride):
                    f"LoD+AO+shadow grids full; render {len(pix)} of {W * H} pixels "
                    f"(every {row_stride}th row); per-step s: vox {t_vox:.2f} "
                    f"illum {t_illum:.2f} render {t_render:.2f}"),
+    }
+
+
+def batched_vs_plain(L, synth, torch, dev, stream, reps):
+    """Plain per-view launches vs one persistent batched launch vs the render
+    server, on 64 views of uneven size over 8 resident line sets."""
+    sets_spec, views_spec = synth.batch_workload_spec()
+    t = time.perf_counter()
+    sets = []
+    for sp in sets_spec:
+        ls = synth.abc_lineset(sp["n_curves"], sp["n_vertices"], sp["seed"], sp["perturb"])
+        with torch.cuda.stream(stream):
+            s = L.lineset_voxelize(torch.as_tensor(ls.curve_off).to(dev), sp["grid"], 32,
+                                   xyz=torch.as_tensor(ls.xyz).to(dev),
+                                   attr=torch.as_tensor(ls.attr).to(dev), stream=stream)
+        sets.append((sp, s))
+        del ls
+    log(f"[bench] batch workload: 8 sets voxelized in {time.perf_counter() - t:.1f}s")
+    lut_op = torch.as_tensor(synth.lut_ramp(1.0)).to(dev)
+    lut_tr = torch.as_tensor(synth.lut_importance_alpha()).to(dev)
+    items = []
+    for v in views_spec:
+        sp, s = sets[v["set"]]
+        cam = synth.look_camera((sp["grid"],) * 3, v["width"], v["height"], v["direction"], False)
+        out = torch.empty((v["height"], v["width"], 4), dtype=torch.float32, device=dev)
+        params = dict(radius=0.4, opaque=sp["opaque"], alpha_stop=0.95, merge_curves=True,
+                      shading=1)
+        items.append((s, cam, lut_op if sp["opaque"] else lut_tr, out, params))
+    rays = sum(it[1].width * it[1].height for it in items)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        stream.synchronize()
+        e0, e1 = ev(), ev()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def plain():
+        for (s, cam, lut, out, params) in items:
+            L.lineset_render(s, cam, lut, out=out, stream=stream, **params)
+
+    plain_ms = timed(plain)
+    t = time.perf_counter()
+    with torch.cuda.stream(stream):
+        b = L.Batch(items, autotune=True, graph=True, stream=stream)
+    tune_s = time.perf_counter() - t
+    batch_ms = timed(lambda: b.render(stream=stream))
+    cfg = b.config()
+    b.close()
+    log(f"[bench] 64 views ({rays / 1e6:.1f} Mrays): plain {plain_ms:.2f} ms, "
+        f"batched {batch_ms:.2f} ms ({cfg})")
+
+    # render server: closed loop (all 64 views submitted at once), then an
+    # open-loop Poisson probe
+    budget = sum(s.info().device_bytes for _, s in sets) + (8 << 30)
+    served = {}
+    srv = L.Server(budget, n_slots=2, max_batch_views=64)
+    ids = [srv.add_lineset(s) for _, s in sets]
+    view_set = [v["set"] for v in views_spec]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in range(reps):
+        tickets = [srv.submit(ids[view_set[k]], it[1], it[2], it[3], **it[4])
+                   for k, it in enumerate(items)]
+        for tk in tickets:
+            srv.wait(tk)
+    closed_s = time.perf_counter() - t
+    st = srv.stats()
+    served["closed_loop"] = dict(mrays_s=rays * reps / closed_s / 1e6, p50_ms=st["p50_ms"],
+                                 p99_ms=st["p99_ms"], mean_batch=st["mean_batch"])
+    srv.close()
+    rng = np.random.default_rng(5)
+    for lam in (100.0, 400.0):
+        srv = L.Server(budget, n_slots=2, max_batch_views=64)
+        ids = [srv.add_lineset(s) for _, s in sets]
+        n_req = int(lam * 1.0)
+        outs = [torch.empty_like(items[k % len(items)][3]) for k in range(n_req)]
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        t0 = time.perf_counter()
+        tickets = []
+        for k in range(n_req):
+            while time.perf_counter() - t0 < arrivals[k]:
+                pass
+            it = items[k % len(items)]
+            tickets.append(srv.submit(ids[view_set[k % len(items)]], it[1], it[2], outs[k], **it[4]))
+        for tk in tickets:
+            srv.wait(tk)
+        st = srv.stats()
+        served[f"poisson_{int(lam)}_per_s"] = dict(requests=n_req, p50_ms=st["p50_ms"],
+                                                  p99_ms=st["p99_ms"], mean_batch=st["mean_batch"],
+                                                  mrays_s=st["mrays_per_s"])
+        srv.close()
+        del outs
+    log(f"[bench] served: {served}")
+    for _, s in sets:
+        s.close()
+    return {
+        "workload": "64 views, area log-uniform 256^2..1920x1080, over 8 sets of 1M..20M "
+                    "segments (128^3..512^3), even sets opaque",
+        "rays_per_batch": rays,
+        "plain_ms": plain_ms,
+        "plain_mrays_s": rays / plain_ms / 1e3,
+        "batched_ms": batch_ms,
+        "batched_mrays_s": rays / batch_ms / 1e3,
+        "batched_over_plain": plain_ms / batch_ms,
+        "batch_config": cfg,
+        "autotune_s": tune_s,
+        "served": served,
     }
 
 
@@ -206,6 +322,8 @@ def main():
         "counters": cnt,
     }
     s.close()
+    if not args.no_batch:
+        result["batched"] = batched_vs_plain(L, synth, torch, dev, stream, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(ls, w, cam, lut_np, light, args.cpu_sample_rows)

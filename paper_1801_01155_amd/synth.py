@@ -236,3 +236,33 @@ WORKLOADS = {
 }
 
 LIGHT_DIR = tuple(float(x) for x in _unit((-0.4, -0.3, -0.87)).astype(np.float32))
+
+
+def batch_workload_spec(seed: int = 4, n_sets: int = 8, n_views: int = 64,
+                        min_segments: float = 1e6, max_segments: float = 20e6,
+                        vertices_per_curve: int = 100):
+    """Sets and views of the batching workload.
+
+    Sets: n_seg_i = min * (max/min)^(i/(n_sets-1)) input segments as curves
+    of 100 vertices; grids 128^3 (i < 3), 256^3 (i < 6), else 512^3; even sets
+    opaque, odd transparent. Views: area log-uniform in [256^2, 1920*1080],
+    aspect 1:1, 4:3 or 16:9, view k on set k mod n_sets, seeded orbit cameras.
+    """
+    rng = np.random.default_rng(seed)
+    sets = []
+    for i in range(n_sets):
+        nseg = min_segments * (max_segments / min_segments) ** (i / max(1, n_sets - 1))
+        n_curves = max(1, int(round(nseg / (vertices_per_curve - 1))))
+        grid = 128 if i < 3 else (256 if i < 6 else 512)
+        sets.append(dict(n_curves=n_curves, n_vertices=vertices_per_curve, seed=100 + i,
+                         perturb=True, grid=grid, opaque=(i % 2 == 0)))
+    views = []
+    lo, hi = np.log(256.0 * 256.0), np.log(1920.0 * 1080.0)
+    for k in range(n_views):
+        area = float(np.exp(rng.uniform(lo, hi)))
+        aspect = [1.0, 4.0 / 3.0, 16.0 / 9.0][int(rng.integers(0, 3))]
+        h = max(16, int(round(np.sqrt(area / aspect))))
+        w = max(16, int(round(h * aspect)))
+        direction = rng.normal(size=3)
+        views.append(dict(set=k % n_sets, width=w, height=h, direction=tuple(direction)))
+    return sets, views

@@ -71,8 +71,8 @@ def test_responses_equal_alone(sets, budget_mb, slots, max_batch):
 
 
 def test_admission_and_errors(sets):
-    resident = sum(s.info().device_bytes for _, s in sets)
-    # budget fits the sets plus ~one 200x150 request at a time
+    resident = sets[0][1].info().device_bytes
+    # budget fits the set plus one 200x150 request at a time
     srv = L.Server(resident + 200 * 150 * 16 + 4096, n_slots=2, max_batch_views=8, max_queue=3)
     sid = srv.add_lineset(sets[0][1])
     grid = sets[0][0]
