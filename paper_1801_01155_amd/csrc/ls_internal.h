@@ -36,7 +36,7 @@ struct ls_lineset {
   int64_t nonempty, max_list;
   uint32_t* offsets;   // [nvox + 1]
   uint64_t* records;   // [n_records] (at least one element allocated)
-  uint64_t* occupancy; // 1 bit per 4^3 macro cell: any record inside
+  uint64_t* occupancy; // per 4^3 macro cell: 64-bit mask of its non-empty voxels
   int32_t macro[3];    // macro-cell grid dims (ceil(grid / 4))
   // density pyramid
   int32_t n_levels;

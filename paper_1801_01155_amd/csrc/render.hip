@@ -692,32 +692,34 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
     // gx + gy + gz steps (the cap only guards against malformed input)
     const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
     int64_t last_mid = -1;
-    unsigned long long last_occ = 0;
+    unsigned long long occ = 0;
     for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
       if (kMode == 0) {
+        // one 64-bit occupancy word per 4^3 macro cell: empty macro cells are
+        // jumped, empty voxels inside stepped over without touching the lists
         const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
         const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
         if (mid != last_mid) {
           last_mid = mid;
-          last_occ = (R.occ[mid >> 6] >> (mid & 63)) & 1ull;
+          occ = R.occ[mid];
           cnt.list_bytes += 8u;
         }
-        if (!last_occ) {
+        if (occ == 0ull) {
           cnt.skips++;
           macro_jump(R, ray, m);
           continue;
         }
-      }
-      cnt.visited++;
-      if (kMode == 0) {
-        const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
-        const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
-        cnt.list_bytes += 8u;
-        if (hi > lo) {
+        cnt.visited++;
+        const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
+        if ((occ >> bit) & 1ull) {
+          const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+          const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
+          cnt.list_bytes += 8u;
           cnt.nonempty++;
           voxel_fast(R, ray, S, dd, inv_dd, lo, hi, acc, cnt);
         }
       } else {
+        cnt.visited++;
         const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
         if (R.offsets[vid + 1] > R.offsets[vid]) cnt.nonempty++;
         voxel_exact(R, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);

@@ -8,7 +8,7 @@
 struct RenderArgs {
   const uint32_t* offsets;
   const uint64_t* records;
-  const unsigned long long* occ;  // 1 bit per 4^3 macro cell
+  const unsigned long long* occ;  // per 4^3 macro cell: mask of non-empty voxels
   int32_t g[3];
   int32_t mg[3];                  // macro grid dims
   float inv_bins;

@@ -297,7 +297,10 @@ __global__ __launch_bounds__(kBlock) void k_list_stats(const uint32_t* offsets, 
   }
 }
 
-// Occupancy of 4^3 macro cells (empty-space skipping in the ray caster).
+// Occupancy mask per 4^3 macro cell: bit (x & 3) + 4 (y & 3) + 16 (z & 3) of
+// the cell's 64-bit word is set when that voxel's list is not empty. One
+// load tells the ray caster which voxels of the macro cell it can skip
+// (a zero word: the whole macro cell).
 __global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, GridArgs ga,
                                                       int32_t mx, int32_t my, int32_t mz,
                                                       unsigned long long* occ) {
@@ -305,23 +308,16 @@ __global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, G
   int64_t nm = (int64_t)mx * my * mz;
   if (m >= nm) return;
   int32_t bx = (int32_t)(m % mx), by = (int32_t)((m / mx) % my), bz = (int32_t)(m / ((int64_t)mx * my));
-  bool any = false;
-  for (int z = 4 * bz; z < 4 * bz + 4 && z < ga.g[2] && !any; ++z)
-    for (int y = 4 * by; y < 4 * by + 4 && y < ga.g[1] && !any; ++y)
-      for (int x = 4 * bx; x < 4 * bx + 4 && x < ga.g[0]; ++x) {
-        int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
-        if (offsets[v + 1] > offsets[v]) {
-          any = true;
-          break;
-        }
-      }
-  if (any) atomicOr(occ + (m >> 6), 1ull << (m & 63));
+  unsigned long long bits = 0;
+  for (int k = 0; k < 64; ++k) {
+    const int32_t x = 4 * bx + (k & 3), y = 4 * by + ((k >> 2) & 3), z = 4 * bz + (k >> 4);
+    if (x >= ga.g[0] || y >= ga.g[1] || z >= ga.g[2]) continue;
+    const int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
+    if (offsets[v + 1] > offsets[v]) bits |= 1ull << k;
+  }
+  occ[m] = bits;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
 
 __global__ __launch_bounds__(kBlock) void k_bbox(const float* xyz, int64_t nv, double* part,
                                                  int* bad) {
@@ -551,11 +547,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   LS_HIP(hipGetLastError());
   for (int a = 0; a < 3; ++a) s->macro[a] = (s->grid[a] + 3) / 4;
   int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
-  int64_t words = (nm + 63) / 64;
-  if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * words))) return rc;
-  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(words)), dim3(kBlock), 0, st,
-                     (unsigned long long*)s->occupancy, words);
-  LS_HIP(hipGetLastError());
+  if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * nm))) return rc;
   hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nm)), dim3(kBlock), 0, st, s->offsets, ga,
                      s->macro[0], s->macro[1], s->macro[2], (unsigned long long*)s->occupancy);
   LS_HIP(hipGetLastError());
