@@ -12,12 +12,13 @@
 // pyramid levels are small enough past level 2 to stay in L2.
 #include "ls_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxCones = 64;
+constexpr int kMaxCones = 32;
 
 struct Pyramid {
   const float* rho;
@@ -34,16 +35,28 @@ struct Cones {
   double dir[kMaxCones][3];
 };
 
+// Sample schedule along a cone: distances s_k < s_max, diameters D_k and
+// levels l_k. With D = max(1, aperture s) and s_{k+1} = s_k + D_k it depends
+// only on the aperture and s_max, so all cones and voxels share it.
+constexpr int kMaxSamples = 48;
+struct Sched {
+  int32_t n;
+  float reach;             // s_max of the schedule + 1 (voxels farther from every face skip inside tests)
+  float s[kMaxSamples];
+  float D[kMaxSamples];
+  int32_t lv[kMaxSamples];
+};
+
 // Trilinear sample of level `lv` at the point v + f (v the voxel corner,
 // integer; f a local offset in voxel units). The level coordinate is formed
 // from v's low bits and f in fp32, so it keeps ~1e-7 cell precision at every
 // level. The two x-neighbour taps are one 8-byte load: the pair starts at
 // j = clamp(i0, 0, D - 2) and the x weight is clamp(x - j, 0, 1), which is
-// clamp-to-edge interpolation.
+// clamp-to-edge interpolation. Level sizes are below 2^31: int32 indices.
 __device__ inline float sample(const Pyramid& P, int lv, const int32_t v[3], const float f[3]) {
   const float scale = __builtin_ldexpf(1.0f, -lv);
   const int32_t mask = (1 << lv) - 1;
-  const int32_t* dm = P.dims[lv];
+  const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
   int32_t i0[3];
   float fr[3];
 #pragma unroll
@@ -54,13 +67,13 @@ __device__ inline float sample(const Pyramid& P, int lv, const int32_t v[3], con
     i0[a] = (v[a] >> lv) + (int32_t)fl;
   }
   const float* r = P.rho + P.off[lv];
-  const int64_t sy = dm[0], sz = (int64_t)dm[0] * dm[1];
-  const int32_t y0 = min(max(i0[1], 0), dm[1] - 1), y1 = min(max(i0[1] + 1, 0), dm[1] - 1);
-  const int32_t z0 = min(max(i0[2], 0), dm[2] - 1), z1 = min(max(i0[2] + 1, 0), dm[2] - 1);
+  const int32_t y0 = min(max(i0[1], 0), dy - 1), y1 = min(max(i0[1] + 1, 0), dy - 1);
+  const int32_t z0 = min(max(i0[2], 0), dz - 1), z1 = min(max(i0[2] + 1, 0), dz - 1);
+  const int32_t rows[4] = {(y0 + dy * z0) * dx, (y1 + dy * z0) * dx, (y0 + dy * z1) * dx,
+                           (y1 + dy * z1) * dx};
   float c[4];
-  const int64_t rows[4] = {y0 * sy + z0 * sz, y1 * sy + z0 * sz, y0 * sy + z1 * sz, y1 * sy + z1 * sz};
-  if (dm[0] >= 2) {
-    const int32_t j = min(max(i0[0], 0), dm[0] - 2);
+  if (dx >= 2) {
+    const int32_t j = min(max(i0[0], 0), dx - 2);
     const float wx = fminf(fmaxf((float)(i0[0] - j) + fr[0], 0.f), 1.f);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -77,52 +90,92 @@ __device__ inline float sample(const Pyramid& P, int lv, const int32_t v[3], con
   return c0 * (1.f - fr[2]) + c1 * fr[2];
 }
 
-// Occlusion along one cone from the centre of voxel v. The inside-the-grid
-// test is made in fp64 on p + s u (the same expression as the definition);
-// the sample itself uses the local offset f = 0.5 + s u in fp32.
-__device__ inline float cone(const Pyramid& P, const int32_t v[3], const double u[3],
-                             double s_max, double aperture) {
-  const int top = P.n_levels - 1;
+// Occlusion along one cone from the centre of voxel v. A sample point
+// p + s u (p the voxel centre) is tested against the grid in fp64, the same
+// expression as the definition; voxels farther than the schedule's reach
+// from every face have all samples inside and skip the test. The sample
+// itself uses the local offset f = 0.5 + s u in fp32.
+__device__ inline float cone(const Pyramid& P, const Sched& S, const int32_t v[3], const double u[3],
+                             bool near_face) {
   const float u32[3] = {(float)u[0], (float)u[1], (float)u[2]};
   float occ = 0.f;
-  double s = 1.0;
-  while (s < s_max) {
-    bool inside = true;
+  for (int k = 0; k < S.n; ++k) {
+    const float s = S.s[k];
+    if (near_face) {
+      bool inside = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double x = ((double)v[a] + 0.5) + s * u[a];
-      inside &= x >= 0.0 && x < (double)P.g[a];
+      for (int a = 0; a < 3; ++a) {
+        const double x = ((double)v[a] + 0.5) + (double)s * u[a];
+        inside &= x >= 0.0 && x < (double)P.g[a];
+      }
+      if (!inside) break;
     }
-    if (!inside) break;
-    double D = aperture * s;
-    D = D < 1.0 ? 1.0 : D;
-    int lv = ilogb(D);
-    lv = lv > top ? top : lv;
-    const float sf = (float)s;
-    const float f[3] = {0.5f + sf * u32[0], 0.5f + sf * u32[1], 0.5f + sf * u32[2]};
-    occ += sample(P, lv, v, f) * (float)D;
+    const float f[3] = {0.5f + s * u32[0], 0.5f + s * u32[1], 0.5f + s * u32[2]};
+    occ += sample(P, S.lv[k], v, f) * S.D[k];
     if (occ >= 1.f) break;
-    s += D;
   }
   return occ < 1.f ? occ : 1.f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ao(Pyramid P, Cones C, int64_t nvox, float* ao) {
-  int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ inline bool near_any_face(const Pyramid& P, const int32_t v[3], float reach) {
+  bool n = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    n |= (float)v[a] < reach || (float)(P.g[a] - 1 - v[a]) < reach;
+  return n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ao(Pyramid P, Cones C, Sched S, int64_t nvox,
+                                               float* ao) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (v >= nvox) return;
   const int32_t p[3] = {(int32_t)(v % P.g[0]), (int32_t)((v / P.g[0]) % P.g[1]),
                         (int32_t)(v / ((int64_t)P.g[0] * P.g[1]))};
+  const bool near_face = near_any_face(P, p, S.reach);
   float sum = 0.f;
-  for (int c = 0; c < C.n; ++c) sum += cone(P, p, C.dir[c], C.s_max, C.aperture);
+  for (int c = 0; c < C.n; ++c) sum += cone(P, S, p, C.dir[c], near_face);
   ao[v] = 1.f - sum / (float)C.n;
 }
 
-__global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, int64_t nvox, float* sh) {
-  int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, Sched S, int64_t nvox,
+                                                   float* sh) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (v >= nvox) return;
   const int32_t p[3] = {(int32_t)(v % P.g[0]), (int32_t)((v / P.g[0]) % P.g[1]),
                         (int32_t)(v / ((int64_t)P.g[0] * P.g[1]))};
-  sh[v] = 1.f - cone(P, p, C.dir[0], INFINITY, C.aperture);
+  sh[v] = 1.f - cone(P, S, p, C.dir[0], near_any_face(P, p, S.reach));
+}
+
+// Builds the schedule; fails (returns false) if it needs more than
+// kMaxSamples entries. Every sample of a cone starting inside the grid lies
+// within distance gmax * sqrt(3) of its voxel, so longer schedules stop there.
+bool make_sched(const ls_lineset* s, double s_max, double aperture, Sched* S) {
+  const int top = s->n_levels - 1;
+  const double limit = 1.7320508075688772 * (double)std::max(s->grid[0], std::max(s->grid[1], s->grid[2])) + 2.0;
+  S->n = 0;
+  double t = 1.0;
+  while (t < s_max && t <= limit) {
+    if (S->n == kMaxSamples) return false;
+    double D = aperture * t;
+    D = D < 1.0 ? 1.0 : D;
+    int lv = std::ilogb(D);
+    lv = lv > top ? top : lv;
+    S->s[S->n] = (float)t;
+    S->D[S->n] = (float)D;
+    S->lv[S->n] = lv;
+    S->n++;
+    t += D;
+  }
+  const double last = S->n ? (double)S->s[S->n - 1] : 0.0;
+  S->reach = (float)(last + 2.0);
+  // the schedule's distances and diameters must be exact in fp32 for the
+  // sample offsets to match the definition
+  for (int k = 0; k < S->n; ++k) {
+    double D = aperture * (double)S->s[k];
+    D = D < 1.0 ? 1.0 : D;
+    if ((double)S->D[k] != D) return false;
+  }
+  return true;
 }
 
 Pyramid make_pyramid(const ls_lineset* s) {
@@ -162,7 +215,13 @@ int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream
     C.dir[i][1] = r * std::sin(ph);
     C.dir[i][2] = z;
   }
-  hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
+  Sched S;
+  if (!make_sched(s, (double)radius, (double)aperture, &S)) {
+    ls_set_error("cone schedule longer than %d samples or not exact in fp32 (aperture too small?)",
+                 kMaxSamples);
+    return LS_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C, S,
                      s->nvox, s->ao);
   LS_HIP(hipGetLastError());
   return LS_OK;
@@ -175,8 +234,14 @@ int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_
   C.n = 1;
   C.aperture = (double)aperture;
   for (int a = 0; a < 3; ++a) C.dir[0][a] = (double)light[a];
+  Sched S;
+  if (!make_sched(s, INFINITY, (double)aperture, &S)) {
+    ls_set_error("cone schedule longer than %d samples or not exact in fp32 (aperture too small?)",
+                 kMaxSamples);
+    return LS_EUNSUPPORTED;
+  }
   hipLaunchKernelGGL(k_shadow, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
-                     s->nvox, s->sh);
+                     S, s->nvox, s->sh);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }

@@ -151,18 +151,25 @@ __device__ inline float grid_lookup(const float* grid, const int32_t g[3], const
   return c0 * (1.f - f[2]) + c1 * f[2];
 }
 
-// Per-ray compositing state.
+// Per-ray compositing state. The merge table (curve tag, end of the open
+// interval) lives in LDS, slot-major with a stride of kBlock so each lane's
+// accesses are conflict-free.
+struct MergeLds {
+  uint32_t tag[kMergeSlots][kBlock];
+  double out[kMergeSlots][kBlock];
+};
+
 struct Accum {
   float C[3] = {0.f, 0.f, 0.f};
   float A = 0.f;
   bool done = false;
-  uint32_t mt_tag[kMergeSlots];
-  double mt_out[kMergeSlots];
-  __device__ Accum() {
+  MergeLds* mt;
+  int lane;
+  __device__ Accum(MergeLds* m, int t) : mt(m), lane(t) {
 #pragma unroll
-    for (int m = 0; m < kMergeSlots; ++m) {
-      mt_tag[m] = 0xFFFFFFFFu;
-      mt_out[m] = -INFINITY;
+    for (int k = 0; k < kMergeSlots; ++k) {
+      mt->tag[k][lane] = 0xFFFFFFFFu;
+      mt->out[k][lane] = -INFINITY;
     }
   }
 };
@@ -170,38 +177,31 @@ struct Accum {
 // Returns true if the hit merges into an open interval of its curve.
 __device__ inline bool merge_hit(Accum& acc, uint32_t tag, double t_in, double t_out,
                                  Counts& cnt) {
+  MergeLds& M = *acc.mt;
+  const int l = acc.lane;
   int f = -1;
 #pragma unroll
   for (int m = 0; m < kMergeSlots; ++m)
-    if (acc.mt_tag[m] == tag) f = m;
+    if (M.tag[m][l] == tag) f = m;
   if (f >= 0) {
-    bool inside = false;
-#pragma unroll
-    for (int m = 0; m < kMergeSlots; ++m) {
-      if (m == f) {
-        inside = t_in <= acc.mt_out[m];
-        acc.mt_out[m] = inside ? fmax(acc.mt_out[m], t_out) : t_out;
-      }
-    }
+    const bool inside = t_in <= M.out[f][l];
+    M.out[f][l] = inside ? fmax(M.out[f][l], t_out) : t_out;
     return inside;
   }
   // new curve: take an empty slot, else evict the interval that closed first
   int slot = 0;
-  double best = acc.mt_out[0];
+  double best = M.out[0][l];
 #pragma unroll
-  for (int m = 1; m < kMergeSlots; ++m)
-    if (acc.mt_out[m] < best) {
-      best = acc.mt_out[m];
+  for (int m = 1; m < kMergeSlots; ++m) {
+    const double o = M.out[m][l];
+    if (o < best) {
+      best = o;
       slot = m;
     }
-#pragma unroll
-  for (int m = 0; m < kMergeSlots; ++m) {
-    if (m == slot) {
-      if (acc.mt_tag[m] != 0xFFFFFFFFu) cnt.evictions++;
-      acc.mt_tag[m] = tag;
-      acc.mt_out[m] = t_out;
-    }
   }
+  if (M.tag[slot][l] != 0xFFFFFFFFu) cnt.evictions++;
+  M.tag[slot][l] = tag;
+  M.out[slot][l] = t_out;
   return false;
 }
 
@@ -212,11 +212,11 @@ struct Shade {
 
 // Shade and composite one fragment. p is the entry point in the frame of
 // `cell`, a/b the record's endpoints in the same frame.
-__device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const Shade& S, Accum& acc, uint64_t rec,
+__device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const float4* lut_lds, const Shade& S, Accum& acc, uint64_t rec,
                                  const int32_t cell[3], const float p[3], const float a[3],
                                  const float b[3], Counts& cnt) {
   const int attr = (int)((rec >> 32) & 0xFF);
-  const float4 lut = reinterpret_cast<const float4*>(R.lut)[attr];
+  const float4 lut = lut_lds[attr];
   const float alpha = R.opaque ? 1.f : lut.w;
   float col[3] = {lut.x, lut.y, lut.z};
   if (R.shading != 0) {
@@ -486,22 +486,25 @@ __device__ inline void local_origin(const Ray& ray, double t, const int32_t cell
 
 // Own-list mode: test the voxel's lines, accept t >= 0, composite in
 // (t, index) order.
-__device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+__device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArgs& R, const float4* lut_lds, const Ray& ray,
+                                  const int32_t vcell[3], double vt0, const Shade& S, float dd,
                                   float inv_dd, uint32_t lo, uint32_t hi, Accum& acc,
                                   Counts& cnt) {
   float q[3];
-  local_origin(ray, ray.t0, ray.cell, q);
-  const float s_min = (float)(-ray.t0);  // t >= 0  <=>  s >= -t0
+  local_origin(ray, vt0, vcell, q);
   if (R.opaque) {
     float best = INFINITY;
     uint32_t bi = 0xFFFFFFFFu;
+    // the next record's load is issued before the current test (one-deep prefetch)
+    uint64_t next = R.records[lo];
     for (uint32_t k = lo; k < hi; ++k) {
-      const uint64_t rec = R.records[k];
+      const uint64_t rec = next;
+      if (k + 1 < hi) next = R.records[k + 1];
       float a[3], b[3], si, so;
       decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
       cnt.tested++;
-      if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && ray.t0 + (double)si >= 0.0) {
+      if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && vt0 + (double)si >= 0.0) {
         cnt.hits++;
         if (si < best || (si == best && k < bi)) {
           best = si;
@@ -517,10 +520,9 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
-      composite(R, S, acc, rec, ray.cell, p, a, b, cnt);
+      composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
       acc.done = true;
     }
-    (void)s_min;
     return;
   }
   float last_t = -INFINITY;
@@ -528,14 +530,16 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
   bool first = true;
   for (;;) {
     HitBuf<float> buf;
+    uint64_t next = R.records[lo];
     for (uint32_t k = lo; k < hi; ++k) {
-      const uint64_t rec = R.records[k];
+      const uint64_t rec = next;
+      if (k + 1 < hi) next = R.records[k + 1];
       float a[3], b[3], si, so;
       decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
       cnt.tested++;
       if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
-      if (!(ray.t0 + (double)si >= 0.0)) continue;
+      if (!(vt0 + (double)si >= 0.0)) continue;
       if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
       if (first) cnt.hits++;
       buf.insert(si, so, k, 0u, rec);
@@ -551,14 +555,14 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
       buf.pop_front();
       if (R.merge) {
         const uint32_t tag = (uint32_t)(rec >> 40);
-        if (merge_hit(acc, tag, ray.t0 + (double)t_in, ray.t0 + (double)t_out, cnt)) continue;
+        if (merge_hit(acc, tag, vt0 + (double)t_in, vt0 + (double)t_out, cnt)) continue;
       }
       float a[3], b[3], p[3];
       decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
-      composite(R, S, acc, rec, ray.cell, p, a, b, cnt);
+      composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
     }
     if (acc.done || !more) break;
     first = false;
@@ -578,7 +582,7 @@ __device__ inline double owner_ref(const Ray& ray, const int32_t w[3], double id
   return s * idd;
 }
 
-__device__ __attribute__((always_inline)) inline void voxel_exact(const RenderArgs& R, const Ray& ray, const Shade& S, float dd,
+__device__ __attribute__((always_inline)) inline void voxel_exact(const RenderArgs& R, const float4* lut_lds, const Ray& ray, const Shade& S, float dd,
                                    float inv_dd, double idd, double t1, Accum& acc, Counts& cnt) {
   double last_t = -INFINITY;
   uint32_t last_i = 0;
@@ -634,7 +638,7 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + s_in * ray.d[c];
-      composite(R, S, acc, rec, w, p, a, b, cnt);
+      composite(R, lut_lds, S, acc, rec, w, p, a, b, cnt);
       if (R.opaque) acc.done = true;
     }
     if (acc.done || !more) break;
@@ -667,11 +671,12 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
 }
 
 template <int kMode>
-__device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, int i, int j, Counts& cnt) {
+__device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, const float4* lut_lds, MergeLds* mt, int i,
+                                                             int j, Counts& cnt) {
   Ray ray;
   make_ray(R, i, j, ray.o, ray.d);
   dda_init(R, ray);
-  Accum acc;
+  Accum acc(mt, threadIdx.x);
   if (ray.alive) {
     const float dd = dot3(ray.d, ray.d);
     const float inv_dd = 1.f / dd;
@@ -691,40 +696,67 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
     // every step moves one cell monotonically along one axis: at most
     // gx + gy + gz steps (the cap only guards against malformed input)
     const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
-    int64_t last_mid = -1;
-    unsigned long long occ = 0;
+    if (kMode == 0) {
+      // Two phases per round ("while-while"): every lane first walks until
+      // it reaches its next non-empty voxel (cheap stepping; one 64-bit
+      // occupancy word per 4^3 macro cell lets empty macro cells be jumped and
+      // empty voxels be stepped over without touching the lists), then all
+      // lanes test their voxel's lines together, so the costly list work runs
+      // with most of the wave active. Each ray still visits its voxels in
+      // order.
+      int64_t last_mid = -1;
+      unsigned long long occ = 0;
+      int it = 0;
+      for (;;) {
+        bool pending = false;
+        int32_t pc[3] = {0, 0, 0};
+        double pt0 = 0.0;
+        uint32_t plo = 0, phi = 0;
+        while (ray.alive && !pending && it < max_steps) {
+          ++it;
+          const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
+          const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
+          if (mid != last_mid) {
+            last_mid = mid;
+            occ = R.occ[mid];
+            cnt.list_bytes += 8u;
+          }
+          if (occ == 0ull) {
+            cnt.skips++;
+            macro_jump(R, ray, m);
+            continue;
+          }
+          cnt.visited++;
+          const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
+          if ((occ >> bit) & 1ull) {
+            const int64_t vid =
+                ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+            plo = R.offsets[vid];
+            phi = R.offsets[vid + 1];
+            pc[0] = ray.cell[0];
+            pc[1] = ray.cell[1];
+            pc[2] = ray.cell[2];
+            pt0 = ray.t0;
+            pending = true;
+            cnt.list_bytes += 8u;
+            cnt.nonempty++;
+          }
+          ray.t0 = dda_step(R, ray);
+        }
+        if (!pending) break;
+        voxel_fast(R, lut_lds, ray, pc, pt0, S, dd, inv_dd, plo, phi, acc, cnt);
+        if (acc.done) break;
+      }
+    } else {
     for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
-      if (kMode == 0) {
-        // one 64-bit occupancy word per 4^3 macro cell: empty macro cells are
-        // jumped, empty voxels inside stepped over without touching the lists
-        const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
-        const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
-        if (mid != last_mid) {
-          last_mid = mid;
-          occ = R.occ[mid];
-          cnt.list_bytes += 8u;
-        }
-        if (occ == 0ull) {
-          cnt.skips++;
-          macro_jump(R, ray, m);
-          continue;
-        }
-        cnt.visited++;
-        const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
-        if ((occ >> bit) & 1ull) {
-          const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
-          const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
-          cnt.list_bytes += 8u;
-          cnt.nonempty++;
-          voxel_fast(R, ray, S, dd, inv_dd, lo, hi, acc, cnt);
-        }
-      } else {
+      {
         cnt.visited++;
         const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
         if (R.offsets[vid + 1] > R.offsets[vid]) cnt.nonempty++;
-        voxel_exact(R, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
+        voxel_exact(R, lut_lds, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
       }
       ray.t0 = dda_step(R, ray);
+    }
     }
   }
   float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
@@ -738,9 +770,16 @@ __device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int l
   j = ty * 8 * R.wy + (wave / R.wx) * 8 + (lane >> 3);
 }
 
-__device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, int i, int j, Counts& cnt) {
-  if (R.mode == 0) render_pixel<0>(R, i, j, cnt);
-  else render_pixel<1>(R, i, j, cnt);
+__device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, const float4* lut_lds, MergeLds* mt, int i, int j,
+                       Counts& cnt) {
+  if (R.mode == 0) render_pixel<0>(R, lut_lds, mt, i, j, cnt);
+  else render_pixel<1>(R, lut_lds, mt, i, j, cnt);
+}
+
+// Stages a view's transfer function (256 RGBA) in LDS.
+__device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
+  for (int k = threadIdx.x; k < 256; k += blockDim.x)
+    lut_lds[k] = reinterpret_cast<const float4*>(R.lut)[k];
 }
 
 template <int kMode, bool kCount>
@@ -752,11 +791,19 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   const int x = b % kXcds, l = b / kXcds;
   const int row = x + kXcds * (l / R.tiles_x);
   const int tile = row * R.tiles_x + l % R.tiles_x;
+  __shared__ float4 lut_lds[256];
+  __shared__ MergeLds merge_lds;
   Counts cnt;
-  if (row * R.tiles_x < R.n_tiles) {
+  if (row * R.tiles_x >= R.n_tiles) {
+    if (kCount) flush_counts(R.counters, cnt);
+    return;
+  }
+  load_lut(R, lut_lds);
+  __syncthreads();
+  {
     int i, j;
     tile_pixel(R, tile, threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if (i < R.W && j < R.H) render_pixel<kMode>(R, i, j, cnt);
+    if (i < R.W && j < R.H) render_pixel<kMode>(R, lut_lds, &merge_lds, i, j, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
@@ -772,6 +819,9 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
                                                          int32_t n_views, BatchQueues q,
                                                          unsigned* __restrict__ counters) {
   __shared__ int s_tile;
+  __shared__ float4 lut_lds[256];
+  __shared__ MergeLds merge_lds;
+  int lut_view = -1;
   const int home = blockIdx.x % kXcds;
   int qi = 0;
   Counts cnt;
@@ -809,9 +859,15 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
     }
     const int v = __builtin_amdgcn_readfirstlane(lo);
     const RenderArgs R = views[v];
+    if (v != lut_view) {
+      load_lut(R, lut_lds);
+      lut_view = v;
+    }
+    __syncthreads();
     int i, j;
     tile_pixel(R, t - tile_start[v], threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, i, j, cnt);
+    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, lut_lds, &merge_lds, i, j, cnt);
+    __syncthreads();
   }
   if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);
 }

@@ -7,12 +7,14 @@
 // exactly (so the emit pass writes without global atomics on a cursor), the
 // sort by a histogram + scan + scatter, and determinism inside a voxel by a
 // rank pass:
-//   k_count   thread per curve: upper bound of the curve's lines (plane
+//   k_count   wave per curve: upper bound of the curve's lines (plane
 //             crossings - 1); validates the input
 //   scan      curve ranges
-//   k_emit    thread per curve: exact integer clipping, quantization and
-//             packing; writes (voxel, record) in curve order and takes the
-//             record's slot in its voxel with one atomic on the histogram
+//   k_emit    wave per curve, lane per segment: exact integer clipping,
+//             quantization and packing; a wave prefix sum numbers the events
+//             along the curve, so lanes write their lines to consecutive slots
+//             (coalesced) in curve order, each taking its rank in its voxel
+//             with one atomic on the histogram
 //   scan      voxel offsets (CSR)
 //   k_scatter thread per emitted line: index into its voxel's range
 //   k_rank    thread per CSR slot: ranks the voxel's lines by emission order
@@ -69,41 +71,6 @@ __device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
 constexpr int kErrOffsets = 1;
 constexpr int kErrRange = 2;
 
-template <bool kFloatIn>
-__global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_t* lat,
-                                                  const int64_t* curve_off, int64_t n_curves,
-                                                  int64_t n_vertices, SnapArgs sa, GridArgs ga,
-                                                  uint64_t* slots, int* err) {
-  int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= n_curves) return;
-  int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
-  if (v0 < 0 || v1 < v0 || v1 > n_vertices || (c == 0 && v0 != 0)) {
-    atomicOr(err, kErrOffsets);
-    slots[c] = 0;
-    return;
-  }
-  uint64_t crossings = 0;
-  int32_t q[3], cell[3];
-  if (v1 > v0) {
-    load_vertex<kFloatIn>(xyz, lat, v0, sa, q);
-    if (!in_range(q, ga)) atomicOr(err, kErrRange);
-    cell[0] = q[0] >> 8;
-    cell[1] = q[1] >> 8;
-    cell[2] = q[2] >> 8;
-  }
-  for (int64_t v = v0 + 1; v < v1; ++v) {
-    load_vertex<kFloatIn>(xyz, lat, v, sa, q);
-    if (!in_range(q, ga)) atomicOr(err, kErrRange);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      int32_t nc = q[a] >> 8;
-      crossings += (uint64_t)abs(nc - cell[a]);
-      cell[a] = nc;
-    }
-  }
-  slots[c] = crossings > 0 ? crossings - 1 : 0;
-}
-
 // floor(num / den) for 0 <= num < 2^31, 0 < den < 2^31, without an integer
 // divide: fp64 quotient, corrected by one step either way.
 __device__ inline int64_t floor_div_pos(int64_t num, int64_t den) {
@@ -129,12 +96,146 @@ __device__ inline uint32_t face_code(int axis, int side, const int64_t xn[3], in
   return (uint32_t)(2 * axis + side) | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
 }
 
-struct Event {
+// One wave per curve; lane l of the wave handles segment s0 + l, 64 segments
+// at a time, so vertex loads and record writes are contiguous across lanes.
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Per-curve count of line slots: plane crossings - 1 (an upper bound of the
+// lines; simultaneous crossings merge into one event). Validates the input.
+template <bool kFloatIn>
+__global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_t* lat,
+                                                  const int64_t* curve_off, int64_t n_curves,
+                                                  int64_t n_vertices, SnapArgs sa, GridArgs ga,
+                                                  uint64_t* slots, int* err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (c >= n_curves) return;  // wave-uniform
+  const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
+  if (v0 < 0 || v1 < v0 || v1 > n_vertices || (c == 0 && v0 != 0)) {
+    if (lane == 0) {
+      atomicOr(err, kErrOffsets);
+      slots[c] = 0;
+    }
+    return;
+  }
+  unsigned long long crossings = 0;
+  bool bad = false;
+  for (int64_t s0 = v0; s0 < v1; s0 += 64) {
+    const int64_t v = s0 + lane;
+    if (v < v1) {
+      int32_t q[3];
+      load_vertex<kFloatIn>(xyz, lat, v, sa, q);
+      bad |= !in_range(q, ga);
+      if (v + 1 < v1) {
+        int32_t r[3];
+        load_vertex<kFloatIn>(xyz, lat, v + 1, sa, r);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) crossings += (unsigned long long)abs((r[a] >> 8) - (q[a] >> 8));
+      }
+    }
+  }
+  if (bad) atomicOr(err, kErrRange);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) crossings += __shfl_xor(crossings, d, 64);
+  if (lane == 0) slots[c] = crossings > 0 ? crossings - 1 : 0;
+}
+
+// An event: the curve crosses from `cell` into the next voxel at the exact
+// point xn / den (xn = point * den, den = |d| of the crossing axis).
+struct Ev {
   int64_t xn[3];
   int64_t den;
-  uint32_t entry_code;
+  uint32_t exit_code, entry_code;
 };
 
+// Enumerates the events of segment P0 -> P1 in order: crossings of the
+// planes x_a = 256 k (up iff P0_a < 256k <= P1_a, down iff P1_a < 256k <=
+// P0_a), ordered by their exact parameter; equal parameters are one event
+// whose face is the lowest axis's. f(ev, cell_before) per event.
+template <typename F>
+__device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], const GridArgs& ga,
+                                      F&& f) {
+  int64_t d[3], k[3];
+  int32_t left[3], cell[3];
+  int sg[3];
+  bool any = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a] = (int64_t)P1[a] - P0[a];
+    const int32_t c0 = P0[a] >> 8, c1 = P1[a] >> 8;
+    cell[a] = c0;
+    sg[a] = d[a] > 0 ? 1 : (d[a] < 0 ? -1 : 0);
+    k[a] = d[a] > 0 ? c0 + 1 : c0;
+    left[a] = abs(c1 - c0);
+    any |= left[a] != 0;
+  }
+  while (any) {
+    int64_t num[3], dn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      num[a] = sg[a] > 0 ? 256 * k[a] - P0[a] : P0[a] - 256 * k[a];
+      dn[a] = sg[a] > 0 ? d[a] : -d[a];
+    }
+    int best = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (left[a] == 0) continue;
+      if (best < 0 || num[a] * dn[best] < num[best] * dn[a]) best = a;
+    }
+    bool grp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      grp[a] = left[a] != 0 && (a == best || num[a] * dn[best] == num[best] * dn[a]);
+    const int fa = grp[0] ? 0 : (grp[1] ? 1 : 2);
+    int32_t ncell[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ncell[a] = cell[a] + (grp[a] ? sg[a] : 0);
+    Ev ev;
+    ev.den = dn[fa];
+    const int64_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + nf * d[b];
+    const int exit_side = (fa == 0 ? sg[0] : (fa == 1 ? sg[1] : sg[2])) > 0 ? 1 : 0;
+    ev.exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
+    ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
+    f(ev, cell);
+    any = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cell[a] = ncell[a];
+      if (grp[a]) {
+        --left[a];
+        k[a] += sg[a];
+      }
+      any |= left[a] != 0;
+    }
+  }
+}
+
+// The last event of the lanes before this one (or of earlier chunks).
+struct Last {
+  int has;
+  long long xn0, xn1, xn2, den;
+  unsigned entry;
+};
+
+__device__ inline Last shfl_up_last(const Last& v, int d) {
+  Last o;
+  o.has = __shfl_up(v.has, d, 64);
+  o.xn0 = __shfl_up(v.xn0, d, 64);
+  o.xn1 = __shfl_up(v.xn1, d, 64);
+  o.xn2 = __shfl_up(v.xn2, d, 64);
+  o.den = __shfl_up(v.den, d, 64);
+  o.entry = __shfl_up(v.entry, d, 64);
+  return o;
+}
+
+// Lines of every curve in curve order: the line inside a voxel runs from
+// one event's entry point to the next event's exit point; it is dropped if
+// the two exact points or the two quantized endpoints coincide. Line r of a
+// curve (between its events r and r + 1) goes to slot slot_off[c] + r;
+// unused slots are marked invalid. Each line takes its rank in its voxel
+// with one atomic on the histogram.
 template <bool kFloatIn>
 __global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
@@ -142,98 +243,98 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t
                                                  const uint64_t* slot_off, uint64_t* rec_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
                                                  uint32_t* hist) {
-  int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= n_curves) return;
-  int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
-  uint64_t w = slot_off[c];
-  const uint64_t w_end = slot_off[c + 1];
-  const uint64_t hi_bits = ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)(c & 0xFFFFFF) << 40);
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (c >= n_curves) return;  // wave-uniform
+  const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
+  const uint64_t w0 = slot_off[c], w_end = slot_off[c + 1];
+  const uint64_t hi_bits =
+      ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)(c & 0xFFFFFF) << 40);
   const int64_t gx = ga.g[0], gxy = (int64_t)ga.g[0] * ga.g[1];
-  Event prev;
-  bool have_prev = false;
-  int32_t P0[3], P1[3], cell[3];
-  if (v1 - v0 >= 2) {
-    load_vertex<kFloatIn>(xyz, lat, v0, sa, P0);
-    cell[0] = P0[0] >> 8;
-    cell[1] = P0[1] >> 8;
-    cell[2] = P0[2] >> 8;
-  }
-  for (int64_t v = v0 + 1; v < v1; ++v) {
-    load_vertex<kFloatIn>(xyz, lat, v, sa, P1);
-    int64_t d[3], k[3];
-    int32_t left[3];
-    int sg[3];
-    bool any = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      d[a] = (int64_t)P1[a] - P0[a];
-      int32_t c0 = P0[a] >> 8, c1 = P1[a] >> 8;
-      sg[a] = d[a] > 0 ? 1 : (d[a] < 0 ? -1 : 0);
-      k[a] = d[a] > 0 ? c0 + 1 : c0;
-      left[a] = abs(c1 - c0);
-      any |= left[a] != 0;
+  Last carry{0, 0, 0, 0, 1, 0u};
+  uint64_t g0 = 0;  // events of the curve before this chunk
+  for (int64_t s0 = v0; s0 + 1 < v1; s0 += 64) {
+    const int64_t i = s0 + lane;
+    const bool valid = i + 1 < v1;
+    int32_t P0[3] = {0, 0, 0}, P1[3] = {0, 0, 0};
+    if (valid) {
+      load_vertex<kFloatIn>(xyz, lat, i, sa, P0);
+      load_vertex<kFloatIn>(xyz, lat, i + 1, sa, P1);
     }
-    while (any) {
-      // crossing parameter of each axis: t_a = num_a / den_a, den_a = |d_a|
-      int64_t num[3], dn[3];
+    // pass 1: number of events and the last one
+    uint32_t e = 0;
+    Last mine{0, 0, 0, 0, 1, 0u};
+    if (valid)
+      for_each_event(P0, P1, ga, [&](const Ev& ev, const int32_t*) {
+        ++e;
+        mine.has = 1;
+        mine.xn0 = ev.xn[0];
+        mine.xn1 = ev.xn[1];
+        mine.xn2 = ev.xn[2];
+        mine.den = ev.den;
+        mine.entry = ev.entry_code;
+      });
+    // exclusive prefix sum of the event counts
+    uint32_t inc = e;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        num[a] = sg[a] > 0 ? 256 * k[a] - P0[a] : P0[a] - 256 * k[a];
-        dn[a] = sg[a] > 0 ? d[a] : -d[a];
-      }
-      int best = -1;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (left[a] == 0) continue;
-        if (best < 0 || num[a] * dn[best] < num[best] * dn[a]) best = a;
-      }
-      bool grp[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        grp[a] = left[a] != 0 && (a == best || num[a] * dn[best] == num[best] * dn[a]);
-      const int fa = grp[0] ? 0 : (grp[1] ? 1 : 2);
-      int32_t ncell[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ncell[a] = cell[a] + (grp[a] ? sg[a] : 0);
-      Event ev;
-      ev.den = dn[fa];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + num[fa] * d[b];
-      const int exit_side = sg[fa] > 0 ? 1 : 0;
-      const uint32_t exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
-      ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
-      if (have_prev && w < w_end) {
-        bool same = prev.xn[0] * ev.den == ev.xn[0] * prev.den &&
-                    prev.xn[1] * ev.den == ev.xn[1] * prev.den &&
-                    prev.xn[2] * ev.den == ev.xn[2] * prev.den;
-        if (same || prev.entry_code == exit_code) {
-          vox_out[w] = LS_INVALID_VOXEL;
-        } else {
-          uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
-          rec_out[w] = (uint64_t)prev.entry_code | ((uint64_t)exit_code << 15) | hi_bits;
-          vox_out[w] = vid;
-          rank_out[w] = atomicAdd(hist + vid, 1u);
-        }
-        ++w;
-      }
-      prev = ev;
-      have_prev = true;
-      any = false;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cell[a] = ncell[a];
-        if (grp[a]) {
-          --left[a];
-          k[a] += sg[a];
-        }
-        any |= left[a] != 0;
-      }
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
     }
-    P0[0] = P1[0];
-    P0[1] = P1[1];
-    P0[2] = P1[2];
+    const uint32_t base = inc - e;
+    const uint32_t total = __shfl(inc, 63, 64);
+    // inclusive "last event so far" scan, then shift by one lane
+    Last acc = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const Last o = shfl_up_last(acc, d);
+      if (lane >= d && !acc.has) acc = o;
+    }
+    Last before = shfl_up_last(acc, 1);
+    if (lane == 0 || !before.has) before = carry;
+    // pass 2: emit the lines ending at this segment's events
+    if (valid && e > 0) {
+      uint64_t g = g0 + base;
+      Last prev = before;
+      for_each_event(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
+        if (prev.has) {
+          const uint64_t w = w0 + (g - 1);
+          if (w < w_end) {
+            const bool same = prev.xn0 * ev.den == ev.xn[0] * prev.den &&
+                              prev.xn1 * ev.den == ev.xn[1] * prev.den &&
+                              prev.xn2 * ev.den == ev.xn[2] * prev.den;
+            if (same || prev.entry == ev.exit_code) {
+              vox_out[w] = LS_INVALID_VOXEL;
+            } else {
+              const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
+              rec_out[w] = (uint64_t)prev.entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
+              vox_out[w] = vid;
+              rank_out[w] = atomicAdd(hist + vid, 1u);
+            }
+          }
+        }
+        prev.has = 1;
+        prev.xn0 = ev.xn[0];
+        prev.xn1 = ev.xn[1];
+        prev.xn2 = ev.xn[2];
+        prev.den = ev.den;
+        prev.entry = ev.entry_code;
+        ++g;
+      });
+    }
+    // carry the chunk's last event
+    Last last;
+    last.has = __shfl(acc.has, 63, 64);
+    last.xn0 = __shfl(acc.xn0, 63, 64);
+    last.xn1 = __shfl(acc.xn1, 63, 64);
+    last.xn2 = __shfl(acc.xn2, 63, 64);
+    last.den = __shfl(acc.den, 63, 64);
+    last.entry = __shfl(acc.entry, 63, 64);
+    if (last.has) carry = last;
+    g0 += total;
   }
-  for (; w < w_end; ++w) vox_out[w] = LS_INVALID_VOXEL;
+  // slots past the curve's last line
+  for (uint64_t w = w0 + (g0 > 0 ? g0 - 1 : 0) + lane; w < w_end; w += 64) vox_out[w] = LS_INVALID_VOXEL;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const uint32_t* rank,
@@ -362,6 +463,9 @@ __global__ __launch_bounds__(kBlock) void k_snap(const float* xyz, int64_t nv, S
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned curve_blocks(int64_t n) {
+  return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock);
+}
 
 struct DeviceBuf {
   void* p = nullptr;
@@ -459,10 +563,10 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   LS_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
   if (C > 0) {
     if (float_in)
-      hipLaunchKernelGGL((k_count<true>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+      hipLaunchKernelGGL((k_count<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
                          curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
     else
-      hipLaunchKernelGGL((k_count<false>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+      hipLaunchKernelGGL((k_count<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
                          curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
     LS_HIP(hipGetLastError());
   }
@@ -501,11 +605,11 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
     return rc;
   if (C > 0) {
     if (float_in)
-      hipLaunchKernelGGL((k_emit<true>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+      hipLaunchKernelGGL((k_emit<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
                          curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     else
-      hipLaunchKernelGGL((k_emit<false>), dim3(blocks_for(C)), dim3(kBlock), 0, st, xyz, lat,
+      hipLaunchKernelGGL((k_emit<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
                          curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     LS_HIP(hipGetLastError());
