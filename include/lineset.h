@@ -131,12 +131,14 @@ void lineset_destroy(ls_lineset_t set);
  *           (s_max = ao_radius)
  *   sh[v] = 1 - occlusion towards light_dir (s_max = infinity)
  *   lut_rgba   device, float [256][4] straight alpha
- * Errors: LS_EINVAL (bad cone count, radius, aperture or light), LS_ENOMEM. */
+ * Errors: LS_EINVAL (bad cone count, radius, aperture or light), LS_ENOMEM;
+ * LS_EUNSUPPORTED when a cone needs more than 48 samples or sample distances
+ * not exact in fp32 (apertures far below 1). */
 typedef struct {
   const float* lut_rgba;
   int32_t opaque;
   int32_t build_ao;
-  int32_t ao_cones;          /* default 16 */
+  int32_t ao_cones;          /* default 16, at most 32 */
   float ao_radius;           /* default 15 voxels */
   float cone_aperture;       /* default 1: the cone subtends one voxel at s = 1 */
   int32_t build_shadow;

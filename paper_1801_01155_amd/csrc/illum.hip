@@ -163,18 +163,14 @@ bool make_sched(const ls_lineset* s, double s_max, double aperture, Sched* S) {
     S->s[S->n] = (float)t;
     S->D[S->n] = (float)D;
     S->lv[S->n] = lv;
+    // distances and diameters must be exact in fp32 for the sample offsets
+    // to match the definition
+    if ((double)S->s[S->n] != t || (double)S->D[S->n] != D) return false;
     S->n++;
     t += D;
   }
   const double last = S->n ? (double)S->s[S->n - 1] : 0.0;
   S->reach = (float)(last + 2.0);
-  // the schedule's distances and diameters must be exact in fp32 for the
-  // sample offsets to match the definition
-  for (int k = 0; k < S->n; ++k) {
-    double D = aperture * (double)S->s[k];
-    D = D < 1.0 ? 1.0 : D;
-    if ((double)S->D[k] != D) return false;
-  }
   return true;
 }
 
