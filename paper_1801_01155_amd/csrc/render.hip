@@ -697,66 +697,48 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
     // gx + gy + gz steps (the cap only guards against malformed input)
     const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
     if (kMode == 0) {
-      // Two phases per round ("while-while"): every lane first walks until
-      // it reaches its next non-empty voxel (cheap stepping; one 64-bit
-      // occupancy word per 4^3 macro cell lets empty macro cells be jumped and
-      // empty voxels be stepped over without touching the lists), then all
-      // lanes test their voxel's lines together, so the costly list work runs
-      // with most of the wave active. Each ray still visits its voxels in
-      // order.
+      // One 64-bit occupancy word per 4^3 macro cell: an empty macro cell is
+      // jumped in one step, and an empty voxel inside an occupied one is
+      // stepped over without touching the lists. (Deferring the list tests
+      // until every lane of the wave has reached a non-empty voxel was
+      // measured slower: the extra live state cost more than the divergence
+      // it removed.)
       int64_t last_mid = -1;
       unsigned long long occ = 0;
-      int it = 0;
-      for (;;) {
-        bool pending = false;
-        int32_t pc[3] = {0, 0, 0};
-        double pt0 = 0.0;
-        uint32_t plo = 0, phi = 0;
-        while (ray.alive && !pending && it < max_steps) {
-          ++it;
-          const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
-          const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
-          if (mid != last_mid) {
-            last_mid = mid;
-            occ = R.occ[mid];
-            cnt.list_bytes += 8u;
-          }
-          if (occ == 0ull) {
-            cnt.skips++;
-            macro_jump(R, ray, m);
-            continue;
-          }
-          cnt.visited++;
-          const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
-          if ((occ >> bit) & 1ull) {
-            const int64_t vid =
-                ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
-            plo = R.offsets[vid];
-            phi = R.offsets[vid + 1];
-            pc[0] = ray.cell[0];
-            pc[1] = ray.cell[1];
-            pc[2] = ray.cell[2];
-            pt0 = ray.t0;
-            pending = true;
-            cnt.list_bytes += 8u;
-            cnt.nonempty++;
-          }
-          ray.t0 = dda_step(R, ray);
+      for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
+        const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
+        const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
+        if (mid != last_mid) {
+          last_mid = mid;
+          occ = R.occ[mid];
+          cnt.list_bytes += 8u;
         }
-        if (!pending) break;
-        voxel_fast(R, lut_lds, ray, pc, pt0, S, dd, inv_dd, plo, phi, acc, cnt);
-        if (acc.done) break;
+        if (occ == 0ull) {
+          cnt.skips++;
+          macro_jump(R, ray, m);
+          continue;
+        }
+        cnt.visited++;
+        const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
+        if ((occ >> bit) & 1ull) {
+          const int64_t vid =
+              ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+          const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
+          cnt.list_bytes += 8u;
+          cnt.nonempty++;
+          voxel_fast(R, lut_lds, ray, ray.cell, ray.t0, S, dd, inv_dd, lo, hi, acc, cnt);
+        }
+        ray.t0 = dda_step(R, ray);
       }
     } else {
-    for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
-      {
+      for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
         cnt.visited++;
-        const int64_t vid = ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+        const int64_t vid =
+            ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
         if (R.offsets[vid + 1] > R.offsets[vid]) cnt.nonempty++;
         voxel_exact(R, lut_lds, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
+        ray.t0 = dda_step(R, ray);
       }
-      ray.t0 = dda_step(R, ray);
-    }
     }
   }
   float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
