@@ -24,6 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_CAL_BYTES = 2 << 30
+
+# HBM bytes the ray caster moves per launch on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
+#   python3 bench.py --steps 1 --warmup 0 --no-batch --no-cpu-baseline --copy-calibration
+# each scaled by the counter's reading for the appended 2 GiB copy (true bytes /
+# counted bytes). The figure holds for the kernel source it was measured on
+# only: bench reports it when csrc/render.hip still has this sha256, else null.
+RENDER_TRAFFIC = None
 
 
 def log(*a):
@@ -41,6 +50,18 @@ def parse():
                     help="skip the batched / served comparison")
     ap.add_argument("--cpu-sample-rows", type=int, default=8,
                     help="oracle renders every k-th image row")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the open-loop serving sweep")
+    ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
+                    help="Poisson arrival rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="arrivals per rate: max(100, rate * seconds), capped")
+    ap.add_argument("--serve-max-requests", type=int, default=2000)
+    ap.add_argument("--serve-inflight-mib", type=float, default=64.0,
+                    help="HBM budget for outputs in flight, beyond the resident sets")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="append one 2 GiB device-to-device copy (the reference kernel "
+                         "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     return ap.parse_args()
 
 
@@ -140,8 +161,7 @@ def batched_vs_plain(L, synth, torch, dev, stream, reps):
     log(f"[bench] 64 views ({rays / 1e6:.1f} Mrays): plain {plain_ms:.2f} ms, "
         f"batched {batch_ms:.2f} ms ({cfg})")
 
-    # render server: closed loop (all 64 views submitted at once), then an
-    # open-loop Poisson probe
+    # render server, closed loop: all 64 views submitted at once
     budget = sum(s.info().device_bytes for _, s in sets) + (8 << 30)
     served = {}
     srv = L.Server(budget, n_slots=2, max_batch_views=64)
@@ -159,28 +179,6 @@ def batched_vs_plain(L, synth, torch, dev, stream, reps):
     served["closed_loop"] = dict(mrays_s=rays * reps / closed_s / 1e6, p50_ms=st["p50_ms"],
                                  p99_ms=st["p99_ms"], mean_batch=st["mean_batch"])
     srv.close()
-    rng = np.random.default_rng(5)
-    for lam in (100.0, 400.0):
-        srv = L.Server(budget, n_slots=2, max_batch_views=64)
-        ids = [srv.add_lineset(s) for _, s in sets]
-        n_req = int(lam * 1.0)
-        outs = [torch.empty_like(items[k % len(items)][3]) for k in range(n_req)]
-        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
-        t0 = time.perf_counter()
-        tickets = []
-        for k in range(n_req):
-            while time.perf_counter() - t0 < arrivals[k]:
-                pass
-            it = items[k % len(items)]
-            tickets.append(srv.submit(ids[view_set[k % len(items)]], it[1], it[2], outs[k], **it[4]))
-        for tk in tickets:
-            srv.wait(tk)
-        st = srv.stats()
-        served[f"poisson_{int(lam)}_per_s"] = dict(requests=n_req, p50_ms=st["p50_ms"],
-                                                  p99_ms=st["p99_ms"], mean_batch=st["mean_batch"],
-                                                  mrays_s=st["mrays_per_s"])
-        srv.close()
-        del outs
     log(f"[bench] served: {served}")
     for _, s in sets:
         s.close()
@@ -196,6 +194,103 @@ def batched_vs_plain(L, synth, torch, dev, stream, reps):
         "batch_config": cfg,
         "autotune_s": tune_s,
         "served": served,
+    }
+
+
+def _lod_dims(grid):
+    """Level sizes of the density pyramid of a cubic grid (halving to 1)."""
+    dims, g = [], grid
+    while True:
+        dims.append((g, g, g))
+        if g == 1:
+            return dims
+        g = (g + 1) // 2
+
+
+def serve_sweep(L, synth, torch, dev, rates, seconds_per_rate, max_requests,
+                inflight_bytes):
+    """Open-loop serving: Poisson arrivals at each rate over 4 resident sets
+    of 1M / 5M / 20M / 50M segments (256^3, 256^3, 512^3, 512^3, AO and
+    shadow grids built); resolution uniform over 512^2 / 1280x720 /
+    1920x1080; transparency and AO shading each on with probability 1/2. The
+    HBM budget is the resident sets plus `inflight_bytes` for outputs in
+    flight, so bursts wait for memory."""
+    sets_spec, reqs = synth.serve_workload_spec(n_requests=max_requests)
+    lut_tr = torch.as_tensor(synth.lut_importance_alpha()).to(dev)
+    lut_op = torch.as_tensor(synth.lut_ramp(1.0)).to(dev)
+    t = time.perf_counter()
+    sets = []
+    for sp in sets_spec:
+        ls = synth.abc_lineset(sp["n_curves"], sp["n_vertices"], sp["seed"], sp["perturb"])
+        s = L.lineset_voxelize(torch.as_tensor(ls.curve_off).to(dev), sp["grid"], 32,
+                               xyz=torch.as_tensor(ls.xyz).to(dev),
+                               attr=torch.as_tensor(ls.attr).to(dev))
+        L.lineset_build_lod(s, lut_tr, opaque=False, build_ao=True, build_shadow=True,
+                            light_dir=synth.LIGHT_DIR)
+        sets.append(s)
+        del ls
+    torch.cuda.synchronize()
+    resident = sum(s.info().device_bytes for s in sets)
+    log(f"[bench] serving sets built in {time.perf_counter() - t:.1f}s "
+        f"({resident / 2**30:.2f} GiB resident)")
+    ring = 16
+    bufs = {wh: [torch.empty((wh[1], wh[0], 4), dtype=torch.float32, device=dev)
+                 for _ in range(ring)] for wh in synth.SERVE_RESOLUTIONS}
+    cams = [synth.look_camera((sets_spec[r["set"]]["grid"],) * 3, r["width"], r["height"],
+                              r["direction"], False) for r in reqs]
+    budget = resident + inflight_bytes
+    rng = np.random.default_rng(55)
+    out = {}
+    for lam in rates:
+        n_req = int(min(max_requests, max(100, lam * seconds_per_rate)))
+        srv = L.Server(budget, n_slots=2, max_batch_views=64)
+        ids = [srv.add_lineset(s) for s in sets]
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        last = {}
+        use = {wh: 0 for wh in bufs}
+        tickets = []
+        collected = set()
+        offered = 0
+        t0 = time.perf_counter()
+        for k in range(n_req):
+            r = reqs[k]
+            wh = (r["width"], r["height"])
+            slot = use[wh] % ring
+            use[wh] += 1
+            prev = last.get((wh, slot))
+            if prev is not None and prev not in collected:
+                srv.wait(prev)          # the ring buffer's previous image is done
+                collected.add(prev)
+            while time.perf_counter() - t0 < arrivals[k]:
+                pass
+            params = dict(radius=0.4, opaque=not r["transparent"], alpha_stop=0.95,
+                          merge_curves=True, shading=2 if r["ao"] else 1,
+                          light_dir=synth.LIGHT_DIR)
+            tk = srv.submit(ids[r["set"]], cams[k], lut_tr if r["transparent"] else lut_op,
+                            bufs[wh][slot], **params)
+            last[(wh, slot)] = tk
+            tickets.append(tk)
+            offered += r["width"] * r["height"]
+        span = time.perf_counter() - t0
+        for tk in tickets:
+            if tk not in collected:
+                srv.wait(tk)
+        st = srv.stats()
+        out[f"{lam:g}_per_s"] = dict(
+            requests=n_req, offered_mrays_s=offered / span / 1e6, p50_ms=st["p50_ms"],
+            p99_ms=st["p99_ms"], max_ms=st["max_ms"], mrays_s=st["mrays_per_s"],
+            mean_batch=st["mean_batch"], held_for_memory=st["held_for_memory"],
+            held_fraction=st["held_for_memory"] / n_req)
+        log(f"[bench] serve {lam:g} req/s: {out[f'{lam:g}_per_s']}")
+        srv.close()
+    for s in sets:
+        s.close()
+    return {
+        "workload": "Poisson arrivals over 4 resident sets of 1M/5M/20M/50M segments "
+                    "(256^3/256^3/512^3/512^3); 512^2, 1280x720, 1920x1080 uniform; "
+                    "transparency and AO each p=1/2",
+        "budget_bytes": int(budget), "resident_bytes": int(resident),
+        "inflight_budget_bytes": int(inflight_bytes), "rates": out,
     }
 
 
@@ -280,6 +375,27 @@ def main():
     render_bytes = cnt["list_bytes"] + 16 * rays
     achieved = render_bytes / (render_ms * 1e-3) / 1e9
     med = {k: float(np.median(v)) for k, v in phase_ms.items()}
+    traffic = None
+    if RENDER_TRAFFIC is not None:
+        import hashlib
+        src = os.path.join(ROOT, "paper_1801_01155_amd", "csrc", "render.hip")
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() == RENDER_TRAFFIC["render_hip_sha256"]:
+                traffic = RENDER_TRAFFIC["bytes_per_launch"]
+    # minimum HBM bytes per phase (inputs read once, outputs written once)
+    G3 = grid ** 3
+    n_rec = int(info.n_records)
+    n_lod = int(sum(int(np.prod(d)) for d in _lod_dims(grid)))
+    phase_bytes = {
+        "voxelize": 12 * int(xyz.shape[0]) + 9 * (int(off.shape[0]) - 1) + 8 * n_rec
+        + 4 * (G3 + 1),
+        "lod_illum": 8 * n_rec + 4 * (G3 + 1) + 3 * 4 * G3 + 4 * n_lod + 2 * 4 * G3,
+        "render": render_bytes,
+    }
+    phase_roof = {k: {"algorithmic_bytes": int(b), "ms": med[k],
+                      "GB_s": b / (med[k] * 1e-3) / 1e9,
+                      "frac_hbm": b / (med[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                  for k, b in phase_bytes.items()}
     log(f"[bench] phases (median ms): {med}; counters {cnt}")
 
     result = {
@@ -315,19 +431,32 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": int(render_bytes),
             "avg_launch_ms": render_ms,
         },
+        "phase_rooflines": phase_roof,
         "counters": cnt,
     }
     s.close()
     if not args.no_batch:
         result["batched"] = batched_vs_plain(L, synth, torch, dev, stream, max(3, args.steps // 2))
+    if not args.no_serve:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        result["serving"] = serve_sweep(L, synth, torch, dev, rates, args.serve_seconds,
+                                        args.serve_max_requests,
+                                        int(args.serve_inflight_mib * 2**20))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(ls, w, cam, lut_np, light, args.cpu_sample_rows)
     print(json.dumps(result), flush=True)
+    if args.copy_calibration:
+        x = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {COPY_CAL_BYTES} bytes done")
 
 
 if __name__ == "__main__":

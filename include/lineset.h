@@ -300,6 +300,8 @@ typedef struct {
   double mean_batch;
   int64_t queued, max_queue_depth, rejected;
   size_t resident_bytes, inflight_bytes;
+  int64_t held_for_memory;   /* requests that waited at the queue head because
+                                their reservation did not fit the budget */
 } ls_server_report;
 
 int ls_server_create(const ls_server_config* cfg, ls_server_t* out);

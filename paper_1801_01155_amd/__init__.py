@@ -385,7 +385,7 @@ class ServerReport(C.Structure):
                 ("max_ms", C.c_double), ("mrays_per_s", C.c_double), ("batches", C.c_int64),
                 ("mean_batch", C.c_double), ("queued", C.c_int64), ("max_queue_depth", C.c_int64),
                 ("rejected", C.c_int64), ("resident_bytes", C.c_size_t),
-                ("inflight_bytes", C.c_size_t)]
+                ("inflight_bytes", C.c_size_t), ("held_for_memory", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

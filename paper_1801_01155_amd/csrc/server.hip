@@ -36,6 +36,7 @@ struct Request {
   size_t bytes;          // reservation against the budget
   Clock::time_point t_submit, t_done;
   int state;             // 0 queued, 1 running, 2 done
+  bool held = false;     // was once at the queue head without room in the budget
 };
 
 constexpr int kQueueWords = 8 + (int)(sizeof(RenderCounters) / sizeof(unsigned));
@@ -73,6 +74,7 @@ struct ls_server {
   // statistics
   std::vector<double> lat_ms;
   uint64_t rays_done = 0, batches = 0, batched_views = 0, rejected = 0, max_depth = 0;
+  uint64_t held = 0;
   bool have_first = false;
   Clock::time_point t_first, t_last;
   int launch_error = 0;
@@ -144,7 +146,13 @@ void scheduler(ls_server* S) {
       if (sl.busy || S->queue.empty()) continue;
       while (!S->queue.empty() && (int)sl.reqs.size() < S->cfg.max_batch_views) {
         Request* r = S->queue.front();
-        if (S->resident + S->inflight + sl.bytes + r->bytes > budget) break;
+        if (S->resident + S->inflight + sl.bytes + r->bytes > budget) {
+          if (!r->held) {
+            r->held = true;
+            S->held++;
+          }
+          break;
+        }
         S->queue.pop_front();
         r->state = 1;
         sl.reqs.push_back(r);
@@ -360,6 +368,7 @@ int ls_server_stats(ls_server_t S, ls_server_report* o) {
   o->queued = (int64_t)S->queue.size();
   o->max_queue_depth = (int64_t)S->max_depth;
   o->rejected = (int64_t)S->rejected;
+  o->held_for_memory = (int64_t)S->held;
   o->resident_bytes = S->resident;
   o->inflight_bytes = S->inflight;
   return LS_OK;

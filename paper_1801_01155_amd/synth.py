@@ -19,6 +19,7 @@ them into grid coordinates is the method's first step and lives on each side.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -75,11 +76,14 @@ def _velocity(x: np.ndarray, modes) -> np.ndarray:
 
 
 def abc_lineset(n_curves: int, n_vertices: int, seed: int,
-                perturb: bool = False, chunk: int = 1 << 18) -> LineSet:
+                perturb: bool = False, chunk: int = 1 << 14, workers: int = 0) -> LineSet:
     """RK4 (dt = 0.01, fp64) streamlines of the (perturbed) ABC flow.
 
     Seeds are uniform in [0, 2 pi]^3 from ``numpy.random.default_rng(seed)``;
     draw order: seeds, perturbation modes (if any), per-curve importance.
+    Curves are integrated in fixed chunks of ``chunk`` curves, spread over
+    ``workers`` threads (0: up to 8); the result does not depend on the
+    number of threads.
     """
     rng = np.random.default_rng(seed)
     seeds = rng.uniform(0.0, 2.0 * math.pi, size=(n_curves, 3))
@@ -89,7 +93,8 @@ def abc_lineset(n_curves: int, n_vertices: int, seed: int,
 
     xyz = np.empty((n_curves, n_vertices, 3), dtype=np.float32)
     h = RK4_DT
-    for c0 in range(0, n_curves, chunk):
+
+    def integrate(c0):
         x = seeds[c0:c0 + chunk].copy()
         xyz[c0:c0 + chunk, 0] = x
         for i in range(1, n_vertices):
@@ -99,6 +104,16 @@ def abc_lineset(n_curves: int, n_vertices: int, seed: int,
             k4 = _velocity(x + h * k3, modes)
             x = x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
             xyz[c0:c0 + chunk, i] = x
+
+    starts = list(range(0, n_curves, chunk))
+    nw = workers if workers > 0 else min(8, os.cpu_count() or 1)
+    if nw > 1 and len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(nw, len(starts))) as ex:
+            list(ex.map(integrate, starts))
+    else:
+        for c0 in starts:
+            integrate(c0)
     curve_off = np.arange(n_curves + 1, dtype=np.int64) * n_vertices
     return LineSet(xyz.reshape(-1, 3), curve_off, attr)
 
@@ -266,3 +281,35 @@ def batch_workload_spec(seed: int = 4, n_sets: int = 8, n_views: int = 64,
         direction = rng.normal(size=3)
         views.append(dict(set=k % n_sets, width=w, height=h, direction=tuple(direction)))
     return sets, views
+
+
+SERVE_RESOLUTIONS = ((512, 512), (1280, 720), (1920, 1080))
+
+
+def serve_workload_spec(seed: int = 5, n_requests: int = 2000,
+                        set_segments=(1e6, 5e6, 20e6, 50e6), grids=(256, 256, 512, 512),
+                        vertices_per_curve: int = 100):
+    """Resident sets and the request stream of the serving workload.
+
+    Sets: curves of 100 vertices with the given input-segment counts and
+    grids (perturbed flow, seeds 200 + i). Requests: set uniform over the
+    sets, resolution uniform over 512^2, 1280x720 and 1920x1080,
+    transparency and AO shading each on with probability 1/2, direction of a
+    random orbit camera. Arrival times are drawn by the caller per rate.
+    """
+    rng = np.random.default_rng(seed)
+    sets = []
+    for i, (nseg, g) in enumerate(zip(set_segments, grids)):
+        n_curves = max(1, int(round(nseg / (vertices_per_curve - 1))))
+        sets.append(dict(n_curves=n_curves, n_vertices=vertices_per_curve, seed=200 + i,
+                         perturb=True, grid=g))
+    reqs = []
+    for _ in range(n_requests):
+        s = int(rng.integers(0, len(sets)))
+        w, h = SERVE_RESOLUTIONS[int(rng.integers(0, len(SERVE_RESOLUTIONS)))]
+        transparent = bool(rng.integers(0, 2))
+        ao = bool(rng.integers(0, 2))
+        direction = tuple(rng.normal(size=3))
+        reqs.append(dict(set=s, width=w, height=h, transparent=transparent, ao=ao,
+                         direction=direction))
+    return sets, reqs

@@ -94,6 +94,7 @@ def test_admission_and_errors(sets):
     st = srv.stats()
     print(f"[admission] {st} busy={busy}", flush=True)
     assert st["completed"] == len(tickets) and st["mean_batch"] <= 1.0 + 1e-9
+    assert 0 <= st["held_for_memory"] <= len(tickets)
     with pytest.raises(L.LinesetError):      # already collected
         srv.wait(tickets[0])
     srv.close()

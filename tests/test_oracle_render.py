@@ -262,3 +262,34 @@ def test_counters_consistent():
     lut = synth.lut_importance_alpha()
     _, k = O.render(csr, grid, 16, cam, mode=0, lut=lut, opaque=False, merge_curves=True)
     assert k["visited"] >= k["nonempty"] and k["tested"] >= k["hits"] >= k["fragments"] > 0
+
+
+def _golden_rows(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if line:
+            rows.append(line)
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows("uniform_slab.txt"), ids=lambda r: "_".join(r[:2]))
+def test_uniform_slab_golden(row):
+    """Uniform-opacity layers against the closed-form values stored in
+    tests/golden/uniform_slab.txt, without and with alpha-termination."""
+    a, n, A_n, n_star = float(row[0]), int(row[1]), float(row[2]), int(row[3])
+    a32 = float(np.float32(a))
+    for layers, tau, expect_k in ((n, 1.01, n), (n_star + 3, 0.95, n_star)):
+        grid = max(16, layers + 4)
+        csr, lut = _stack(layers, a, grid)
+        cam = _cam((5.3, 8.0 + 0.5 / 32, grid + 10.0), (0, 0, -1), (0.5, 0, 0), (0, 0.5, 0),
+                   9, 9, True)
+        img, _ = O.render(csr, grid, 32, cam, mode=1, lut=lut, radius=0.4, opaque=False,
+                          alpha_stop=tau, merge_curves=True, shading=0)
+        A = img[4, 4, 3]
+        if layers == n:
+            # the table's decimal value; the LUT holds alpha rounded to fp32
+            assert abs(A - A_n) < 2e-7 * n
+        assert math.isclose(A, 1 - (1 - a32) ** expect_k, abs_tol=1e-12)

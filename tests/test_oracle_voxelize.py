@@ -22,9 +22,17 @@ def _rec(entry, exit_, attr=255, curve=0):
     return entry | (exit_ << 15) | (attr << 32) | (curve << 40)
 
 
-# --- Memory statistics: 4 / 5 / 6 bytes for N in (4, 8) / (16, 32) / (64, 128)
+# --- Memory statistics: bytes per line as printed (tests/golden/record_bytes.txt)
 def test_paper_record_bytes():
-    assert [O.paper_record_bytes(n) for n in (4, 8, 16, 32, 64, 128)] == [4, 4, 5, 5, 6, 6]
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "record_bytes.txt")
+    rows = [l.split("#", 1)[0].split() for l in open(path)]
+    rows = [r for r in rows if r and r[0] != "header_bytes"]
+    assert len(rows) == 6
+    for n, nbytes, bin_bits in rows:
+        n = int(n)
+        assert O.paper_record_bytes(n) == int(nbytes)
+        assert 2 * int(math.log2(n)) == int(bin_bits)
 
 
 # --- Curve voxelization, grid set-up ------------------------------------------------
