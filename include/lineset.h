@@ -313,6 +313,20 @@ int ls_server_stats(ls_server_t server, ls_server_report* out);
 void ls_server_destroy(ls_server_t server);   /* finishes queued work first */
 
 /* ------------------------------------------------------------------------ */
+/* Device memory cache. The library takes every device buffer it owns (set
+ * arrays, voxelizer temporaries) from a per-device cache: released blocks
+ * are kept and handed out again to requests that fit (sizes rounded up to a
+ * power of two below 1 MiB, to a multiple of 2 MiB above), so repeated work
+ * of one shape does not call hipMalloc / hipFree. lineset_destroy waits for
+ * the device before its blocks return to the cache. Cached blocks go back to
+ * the runtime when an allocation fails, or here:
+ *   lineset_pool_trim: frees every cached (not live) block on every device.
+ *   lineset_pool_stats: bytes cached (free, kept) and held (live + cached) on
+ *     `device`; LS_EINVAL for a negative device. */
+void lineset_pool_trim(void);
+int lineset_pool_stats(int32_t device, size_t* cached_bytes, size_t* held_bytes);
+
+/* ------------------------------------------------------------------------ */
 /* Inspection. */
 typedef struct {
   int32_t grid[3];

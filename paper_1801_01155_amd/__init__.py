@@ -262,6 +262,22 @@ def lineset_info(ls: LineSet) -> Info:
     return i
 
 
+def lineset_pool_trim() -> None:
+    """Frees the device memory cache's unused blocks (all devices)."""
+    L = lib()
+    L.lineset_pool_trim.restype = None
+    L.lineset_pool_trim()
+
+
+def lineset_pool_stats(device: int = 0) -> dict:
+    """{'cached_bytes', 'held_bytes'} of the device memory cache on `device`."""
+    c, h = C.c_size_t(0), C.c_size_t(0)
+    L = lib()
+    L.lineset_pool_stats.argtypes = [C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    _check(L.lineset_pool_stats(C.c_int32(device), C.byref(c), C.byref(h)))
+    return {"cached_bytes": c.value, "held_bytes": h.value}
+
+
 _EXPORT_DTYPE = {EXPORT_OFFSETS: torch.int32, EXPORT_RECORDS: torch.int64,
                  EXPORT_LOD_COUNT: torch.float32, EXPORT_LOD_LEN: torch.float32,
                  EXPORT_LOD_RHO: torch.float32, EXPORT_AO: torch.float32,

@@ -48,11 +48,8 @@ int to_device(const T* p, int64_t n, bool on_device, T** out, std::vector<void*>
   }
   void* d = nullptr;
   size_t bytes = sizeof(T) * (size_t)(n > 0 ? n : 1);
-  if (hipMalloc(&d, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    ls_set_error("device allocation of %zu bytes failed", bytes);
-    return LS_ENOMEM;
-  }
+  int rc = pool_alloc(bytes, &d, nullptr);
+  if (rc) return rc;
   owned.push_back(d);
   if (n > 0) LS_HIP(hipMemcpyAsync(d, p, sizeof(T) * (size_t)n, hipMemcpyHostToDevice, st));
   *out = static_cast<T*>(d);
@@ -64,7 +61,7 @@ struct Owned {
   hipStream_t st = nullptr;
   ~Owned() {
     if (!v.empty()) (void)hipStreamSynchronize(st);
-    for (void* p : v) (void)hipFree(p);
+    for (void* p : v) pool_free(p);
   }
 };
 
@@ -78,22 +75,21 @@ void ls_set_error(const char* fmt, ...) {
 }
 
 int ls_alloc(ls_lineset* s, void** p, size_t bytes) {
-  *p = nullptr;
-  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    ls_set_error("device allocation of %zu bytes failed", bytes);
-    return LS_ENOMEM;
-  }
-  s->bytes += bytes;
+  size_t got = 0;
+  const int rc = pool_alloc(bytes, p, &got);
+  if (rc) return rc;
+  s->bytes += got;
   return LS_OK;
 }
 
 void ls_free_all(ls_lineset* s) {
   void* ptrs[] = {s->offsets, s->records, s->occupancy, s->lod_count, s->lod_len,
                   s->lod_rho, s->ao,      s->sh};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  bool any = false;
+  for (void* p : ptrs) any = any || p;
+  // work queued on any stream may still read the set (hipFree would wait too)
+  if (any) (void)hipDeviceSynchronize();
+  for (void* p : ptrs) pool_free(p);
   s->offsets = nullptr;
   s->records = nullptr;
   s->occupancy = nullptr;
@@ -332,11 +328,7 @@ int lineset_render_counted(ls_lineset_t s, const ls_camera* cam, const ls_render
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   RenderCounters* dc = nullptr;
-  if (hipMalloc(&dc, sizeof(RenderCounters)) != hipSuccess) {
-    (void)hipGetLastError();
-    ls_set_error("device allocation failed");
-    return LS_ENOMEM;
-  }
+  if ((rc = pool_alloc(sizeof(RenderCounters), (void**)&dc, nullptr))) return rc;
   RenderCounters h{};
   rc = LS_OK;
   if (hipMemcpyAsync(dc, &h, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess) rc = LS_EDEVICE;
@@ -346,7 +338,8 @@ int lineset_render_counted(ls_lineset_t s, const ls_camera* cam, const ls_render
     ls_set_error("lineset_render_counted: copy of counters failed");
     rc = LS_EDEVICE;
   }
-  (void)hipFree(dc);
+  (void)hipStreamSynchronize(st);
+  pool_free(dc);
   if (rc) return rc;
   counters->visited = (int64_t)h.visited;
   counters->nonempty = (int64_t)h.nonempty;

@@ -146,6 +146,120 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, Sched S, 
   sh[v] = 1.f - cone(P, S, p, C.dir[0], near_any_face(P, p, S.reach));
 }
 
+// LDS-tiled cone tracing. A block handles an 8^3 tile of voxels. Every
+// sample k of every cone lies within s_k (voxel units) of its voxel, so on
+// level l the taps of the whole tile fall inside a box of
+// (tile extent on l) + 2 m_l cells per axis, m_l = ceil(max s_k / 2^l) + 2
+// over the samples on l. The block first copies each level's box into LDS
+// (coordinates clamped to the level, which makes plain trilinear
+// interpolation of the copy the clamp-to-edge interpolation of the level),
+// then every sample reads its 8 taps from LDS. The per-sample arithmetic is
+// that of sample(); only the source of the taps differs.
+constexpr int kTile = 8;
+constexpr int kTileThreads = 256;
+constexpr int kTileSlots = 16;
+constexpr int kTileLdsFloats = 12288;   // 48 KB
+
+struct TileLevels {
+  int32_t n;                        // distinct levels of the schedule
+  int32_t lv[kTileSlots];
+  int32_t m[kTileSlots];            // margin per side, cells
+  int32_t sz[kTileSlots];           // box edge, cells
+  int32_t base[kTileSlots + 1];     // LDS offset (floats) of each box; base[n] = total
+  int32_t slot[kMaxSamples];        // box of each sample
+  int32_t tiles[3];
+  int32_t tiles_per_xcd;
+};
+
+__device__ inline float sample_lds(const float* __restrict__ lds, const TileLevels& TL, int q,
+                                   int lv, const int32_t v[3], const int32_t t0[3],
+                                   const float f[3]) {
+  const float scale = __builtin_ldexpf(1.0f, -lv);
+  const int32_t mask = (1 << lv) - 1;
+  const int sz = TL.sz[q];
+  int32_t li[3];
+  float fr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = ((float)(v[a] & mask) + f[a]) * scale - 0.5f;
+    const float fl = floorf(x);
+    fr[a] = x - fl;
+    const int32_t i0 = (v[a] >> lv) + (int32_t)fl;
+    li[a] = min(max(i0 - ((t0[a] >> lv) - TL.m[q]), 0), sz - 2);
+  }
+  const float* b = lds + TL.base[q] + (li[2] * sz + li[1]) * sz + li[0];
+  const int sy = sz, sz2 = sz * sz;
+  const float* rows[4] = {b, b + sy, b + sz2, b + sz2 + sy};
+  float c[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = rows[k][0] + fr[0] * (rows[k][1] - rows[k][0]);
+  const float c0 = c[0] * (1.f - fr[1]) + c[1] * fr[1];
+  const float c1 = c[2] * (1.f - fr[1]) + c[3] * fr[1];
+  return c0 * (1.f - fr[2]) + c1 * fr[2];
+}
+
+// out[v] = 1 - (mean over the cones of the occlusion), for AO (n cones) and
+// the shadow grid (one cone toward the light).
+__global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C, Sched S,
+                                                              TileLevels TL, float* out) {
+  extern __shared__ float lds[];
+  // XCD x (= block mod 8) works through a contiguous run of tiles, so the
+  // boxes neighbouring tiles share are fetched into one L2.
+  const int b = blockIdx.x;
+  const int tile = (b % 8) * TL.tiles_per_xcd + b / 8;
+  const int nt = TL.tiles[0] * TL.tiles[1] * TL.tiles[2];
+  if (tile >= nt) return;
+  const int32_t t0[3] = {kTile * (tile % TL.tiles[0]),
+                         kTile * ((tile / TL.tiles[0]) % TL.tiles[1]),
+                         kTile * (tile / (TL.tiles[0] * TL.tiles[1]))};
+  for (int q = 0; q < TL.n; ++q) {
+    const int lv = TL.lv[q], sz = TL.sz[q], n = sz * sz * sz;
+    const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
+    const int32_t o0 = (t0[0] >> lv) - TL.m[q], o1 = (t0[1] >> lv) - TL.m[q],
+                  o2 = (t0[2] >> lv) - TL.m[q];
+    const float* __restrict__ r = P.rho + P.off[lv];
+    float* box = lds + TL.base[q];
+    for (int i = threadIdx.x; i < n; i += kTileThreads) {
+      const int lx = i % sz, ly = (i / sz) % sz, lz = i / (sz * sz);
+      const int32_t x = min(max(o0 + lx, 0), dx - 1), y = min(max(o1 + ly, 0), dy - 1),
+                    z = min(max(o2 + lz, 0), dz - 1);
+      box[i] = r[(z * dy + y) * dx + x];
+    }
+  }
+  __syncthreads();
+  const float inv_n = 1.f / (float)C.n;
+#pragma unroll 1
+  for (int half = 0; half < kTile * kTile * kTile / kTileThreads; ++half) {
+    const int loc = threadIdx.x + half * kTileThreads;
+    const int32_t v[3] = {t0[0] + (loc & 7), t0[1] + ((loc >> 3) & 7), t0[2] + (loc >> 6)};
+    if (v[0] >= P.g[0] || v[1] >= P.g[1] || v[2] >= P.g[2]) continue;
+    const bool near_face = near_any_face(P, v, S.reach);
+    float sum = 0.f;
+    for (int c = 0; c < C.n; ++c) {
+      const double* u = C.dir[c];
+      const float u32[3] = {(float)u[0], (float)u[1], (float)u[2]};
+      float occ = 0.f;
+      for (int k = 0; k < S.n; ++k) {
+        const float s = S.s[k];
+        if (near_face) {
+          bool inside = true;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const double x = ((double)v[a] + 0.5) + (double)s * u[a];
+            inside &= x >= 0.0 && x < (double)P.g[a];
+          }
+          if (!inside) break;
+        }
+        const float f[3] = {0.5f + s * u32[0], 0.5f + s * u32[1], 0.5f + s * u32[2]};
+        occ += sample_lds(lds, TL, TL.slot[k], S.lv[k], v, t0, f) * S.D[k];
+        if (occ >= 1.f) break;
+      }
+      sum += occ < 1.f ? occ : 1.f;
+    }
+    out[v[0] + (int64_t)P.g[0] * (v[1] + (int64_t)P.g[1] * v[2])] = 1.f - sum * inv_n;
+  }
+}
+
 // Builds the schedule; fails (returns false) if it needs more than
 // kMaxSamples entries. Every sample of a cone starting inside the grid lies
 // within distance gmax * sqrt(3) of its voxel, so longer schedules stop there.
@@ -188,6 +302,59 @@ Pyramid make_pyramid(const ls_lineset* s) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Boxes of the tiled kernel for schedule S; false if they exceed the LDS
+// budget (then the untiled kernels run).
+bool make_tile_levels(const ls_lineset* s, const Sched& S, TileLevels* T) {
+  *T = TileLevels{};
+  for (int k = 0; k < S.n; ++k) {
+    const int lv = S.lv[k];
+    int q = 0;
+    while (q < T->n && T->lv[q] != lv) ++q;
+    if (q == T->n) {
+      if (T->n == kTileSlots) return false;
+      T->lv[q] = lv;
+      T->m[q] = 0;
+      T->n++;
+    }
+    const int m = (int)std::ceil((double)S.s[k] / (double)(1 << lv)) + 2;
+    T->m[q] = std::max(T->m[q], m);
+    T->slot[k] = q;
+  }
+  int64_t total = 0;
+  for (int q = 0; q < T->n; ++q) {
+    const int ext = std::max(kTile >> T->lv[q], 1);
+    T->sz[q] = ext + 2 * T->m[q];
+    T->base[q] = (int32_t)total;
+    total += (int64_t)T->sz[q] * T->sz[q] * T->sz[q];
+    if (total > kTileLdsFloats) return false;
+  }
+  T->base[T->n] = (int32_t)total;
+  for (int a = 0; a < 3; ++a) T->tiles[a] = (s->grid[a] + kTile - 1) / kTile;
+  const int64_t nt = (int64_t)T->tiles[0] * T->tiles[1] * T->tiles[2];
+  T->tiles_per_xcd = (int32_t)((nt + 7) / 8);
+  return true;
+}
+
+int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
+                 bool ao) {
+  // the tiled kernel pays one LDS fill per tile; with few samples per voxel
+  // (the single shadow cone) direct gathers are cheaper
+  TileLevels T;
+  if (C.n >= 4 && make_tile_levels(s, S, &T)) {
+    const size_t lds = sizeof(float) * (size_t)T.base[T.n];
+    hipLaunchKernelGGL(k_cones_tiled, dim3((unsigned)(8 * T.tiles_per_xcd)), dim3(kTileThreads),
+                       lds, st, make_pyramid(s), C, S, T, out);
+  } else if (ao) {
+    hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
+                       S, s->nvox, out);
+  } else {
+    hipLaunchKernelGGL(k_shadow, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s),
+                       C, S, s->nvox, out);
+  }
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 }  // namespace
 
 int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st) {
@@ -217,10 +384,7 @@ int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream
                  kMaxSamples);
     return LS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C, S,
-                     s->nvox, s->ao);
-  LS_HIP(hipGetLastError());
-  return LS_OK;
+  return launch_cones(s, C, S, s->ao, st, true);
 }
 
 int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_t st) {
@@ -236,8 +400,5 @@ int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_
                  kMaxSamples);
     return LS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_shadow, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
-                     S, s->nvox, s->sh);
-  LS_HIP(hipGetLastError());
-  return LS_OK;
+  return launch_cones(s, C, S, s->sh, st, false);
 }

@@ -52,9 +52,15 @@ struct ls_lineset {
   int device;
 };
 
-// Device allocation tracked on the set.
+// Device allocation tracked on the set (from the device memory cache).
 int ls_alloc(ls_lineset* s, void** p, size_t bytes);
 void ls_free_all(ls_lineset* s);
+
+// Device memory cache (pool.hip): blocks of the current device, rounded up;
+// `rounded` (optional) receives the block size. pool_free requires that no
+// queued device work still uses the block.
+int pool_alloc(size_t bytes, void** out, size_t* rounded);
+void pool_free(void* p);
 
 // ---------------------------------------------------------------------------
 // Scans (scan.hip). out may alias in; writes n + 1 values (out[n] = total).

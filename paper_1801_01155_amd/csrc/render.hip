@@ -2,11 +2,13 @@
 // Raycasting", "Ray-tube intersections", "Rendering effects", "Transparency
 // rendering").
 //
-// One ray per lane; a workgroup of 256 lanes renders a 16 x 16 screen tile as
-// four 8 x 8 wave tiles, so the 64 rays of a wave walk nearly the same voxels
-// and their list loads coalesce in the L1/L2. Workgroups are mapped to tiles
-// so that each of the 8 XCDs (one L2 each) renders one horizontal band of the
-// screen rather than every 8th tile.
+// One ray per lane; a wave renders an 8 x 8 screen tile, so its 64 rays walk
+// nearly the same voxels and their list loads coalesce in the L1/L2. The
+// plain launch uses one wave per workgroup (a finished wave frees its slot
+// at once; measured faster than 2 x 2-wave workgroups on dense frames).
+// Workgroup b runs on XCD b mod 8, and XCD x renders tile rows x, x + 8, ...
+// so neighbouring tiles share one L2 and every XCD gets part of the busy
+// screen region.
 //
 // Per ray:
 //  1. ray from the camera in fp64, rounded to fp32 (these fp32 values are the
@@ -14,14 +16,16 @@
 //  2. clip to the grid box and walk it voxel by voxel (3D-DDA) with the
 //     next crossing of each axis t = (plane - o) * (1/d) in fp64, ties to the
 //     lowest axis: voxel order and [t0, t1) match the CPU oracle bit for bit;
+//     an empty 4^3 macro cell (one 64-bit occupancy word) is crossed in one
+//     step;
 //  3. per non-empty voxel, capsule tests in fp32 in a voxel-local frame
 //     (origin = ray point at t0 minus the voxel corner, formed in fp64);
-//  4. accepted hits go into an 8-slot register-resident sorted buffer keyed
+//  4. accepted hits go into a 4-slot register-resident sorted buffer keyed
 //     by (entry t, record index); a voxel with more hits is swept again for
-//     the next 8 (rare);
-//  5. per hit in order: per-curve interval merge in an 8-entry register
-//     table (the oldest interval is evicted when full), shading, premultiplied
-//     front-to-back compositing, termination at alpha_stop.
+//     the next 4;
+//  5. per hit in order: per-curve interval merge in an 8-entry LDS table
+//     (the interval that closed first is evicted when full), shading,
+//     premultiplied front-to-back compositing, termination at alpha_stop.
 #include "render_args.h"
 
 namespace {
@@ -152,24 +156,42 @@ __device__ inline float grid_lookup(const float* grid, const int32_t g[3], const
 }
 
 // Per-ray compositing state. The merge table (curve tag, end of the open
-// interval) lives in LDS, slot-major with a stride of kBlock so each lane's
-// accesses are conflict-free.
+// interval) lives in dynamically sized LDS, one block per wave, slot-major
+// with a stride of 64 lanes so each lane's accesses are conflict-free and
+// every slot is a constant offset from one base: per thread kMergeSlots
+// doubles and kMergeSlots tags (12 * kMergeSlots bytes).
+constexpr int kWave = 64;
+
 struct MergeLds {
-  uint32_t tag[kMergeSlots][kBlock];
-  double out[kMergeSlots][kBlock];
+  double* out;     // this lane's slot 0; slot k at out[k * 64]
+  uint32_t* tag;   // this lane's slot 0; slot k at tag[k * 64]
 };
+
+// Per wave: [kMergeSlots][64] doubles, then [kMergeSlots][64] tags.
+__device__ inline MergeLds merge_lds_view(double* base) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  double* w = base + wave * (kMergeSlots * kWave * 3 / 2);
+  MergeLds m;
+  m.out = w + lane;
+  m.tag = reinterpret_cast<uint32_t*>(w + kMergeSlots * kWave) + lane;
+  return m;
+}
+
+inline size_t merge_lds_bytes(unsigned threads) {
+  return (size_t)threads * kMergeSlots * (sizeof(double) + sizeof(uint32_t));
+}
 
 struct Accum {
   float C[3] = {0.f, 0.f, 0.f};
   float A = 0.f;
   bool done = false;
-  MergeLds* mt;
-  int lane;
-  __device__ Accum(MergeLds* m, int t) : mt(m), lane(t) {
+  MergeLds mt;
+  __device__ Accum(const MergeLds& m) : mt(m) {
 #pragma unroll
     for (int k = 0; k < kMergeSlots; ++k) {
-      mt->tag[k][lane] = 0xFFFFFFFFu;
-      mt->out[k][lane] = -INFINITY;
+      mt.tag[k * kWave] = 0xFFFFFFFFu;
+      mt.out[k * kWave] = -INFINITY;
     }
   }
 };
@@ -177,31 +199,31 @@ struct Accum {
 // Returns true if the hit merges into an open interval of its curve.
 __device__ inline bool merge_hit(Accum& acc, uint32_t tag, double t_in, double t_out,
                                  Counts& cnt) {
-  MergeLds& M = *acc.mt;
-  const int l = acc.lane;
+  const MergeLds& M = acc.mt;
+  const int l = 0, st = kWave;
   int f = -1;
 #pragma unroll
   for (int m = 0; m < kMergeSlots; ++m)
-    if (M.tag[m][l] == tag) f = m;
+    if (M.tag[m * st + l] == tag) f = m;
   if (f >= 0) {
-    const bool inside = t_in <= M.out[f][l];
-    M.out[f][l] = inside ? fmax(M.out[f][l], t_out) : t_out;
+    const bool inside = t_in <= M.out[f * st + l];
+    M.out[f * st + l] = inside ? fmax(M.out[f * st + l], t_out) : t_out;
     return inside;
   }
   // new curve: take an empty slot, else evict the interval that closed first
   int slot = 0;
-  double best = M.out[0][l];
+  double best = M.out[0 * st + l];
 #pragma unroll
   for (int m = 1; m < kMergeSlots; ++m) {
-    const double o = M.out[m][l];
+    const double o = M.out[m * st + l];
     if (o < best) {
       best = o;
       slot = m;
     }
   }
-  if (M.tag[slot][l] != 0xFFFFFFFFu) cnt.evictions++;
-  M.tag[slot][l] = tag;
-  M.out[slot][l] = t_out;
+  if (M.tag[slot * st + l] != 0xFFFFFFFFu) cnt.evictions++;
+  M.tag[slot * st + l] = tag;
+  M.out[slot * st + l] = t_out;
   return false;
 }
 
@@ -671,12 +693,12 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
 }
 
 template <int kMode>
-__device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, const float4* lut_lds, MergeLds* mt, int i,
+__device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, const float4* lut_lds, const MergeLds& mt, int i,
                                                              int j, Counts& cnt) {
   Ray ray;
   make_ray(R, i, j, ray.o, ray.d);
   dda_init(R, ray);
-  Accum acc(mt, threadIdx.x);
+  Accum acc(mt);
   if (ray.alive) {
     const float dd = dot3(ray.d, ray.d);
     const float inv_dd = 1.f / dd;
@@ -752,7 +774,7 @@ __device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int l
   j = ty * 8 * R.wy + (wave / R.wx) * 8 + (lane >> 3);
 }
 
-__device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, const float4* lut_lds, MergeLds* mt, int i, int j,
+__device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, const float4* lut_lds, const MergeLds& mt, int i, int j,
                        Counts& cnt) {
   if (R.mode == 0) render_pixel<0>(R, lut_lds, mt, i, j, cnt);
   else render_pixel<1>(R, lut_lds, mt, i, j, cnt);
@@ -765,7 +787,7 @@ __device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
 }
 
 template <int kMode, bool kCount>
-__global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
+__global__ __launch_bounds__(kBlock, 4) void k_render(RenderArgs R) {
   // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
   // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every XCD
   // gets a share of the part of the screen the grid covers.
@@ -774,7 +796,8 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   const int row = x + kXcds * (l / R.tiles_x);
   const int tile = row * R.tiles_x + l % R.tiles_x;
   __shared__ float4 lut_lds[256];
-  __shared__ MergeLds merge_lds;
+  extern __shared__ double dyn_lds[];
+  const MergeLds merge_lds = merge_lds_view(dyn_lds);
   Counts cnt;
   if (row * R.tiles_x >= R.n_tiles) {
     if (kCount) flush_counts(R.counters, cnt);
@@ -785,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   {
     int i, j;
     tile_pixel(R, tile, threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if (i < R.W && j < R.H) render_pixel<kMode>(R, lut_lds, &merge_lds, i, j, cnt);
+    if (i < R.W && j < R.H) render_pixel<kMode>(R, lut_lds, merge_lds, i, j, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
@@ -802,7 +825,8 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
                                                          unsigned* __restrict__ counters) {
   __shared__ int s_tile;
   __shared__ float4 lut_lds[256];
-  __shared__ MergeLds merge_lds;
+  extern __shared__ double dyn_lds[];
+  const MergeLds merge_lds = merge_lds_view(dyn_lds);
   int lut_view = -1;
   const int home = blockIdx.x % kXcds;
   int qi = 0;
@@ -848,7 +872,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
     __syncthreads();
     int i, j;
     tile_pixel(R, t - tile_start[v], threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, lut_lds, &merge_lds, i, j, cnt);
+    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, lut_lds, merge_lds, i, j, cnt);
     __syncthreads();
   }
   if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);
@@ -905,12 +929,13 @@ int launch_render(const RenderArgs& R, hipStream_t st) {
   const int tiles_y = R.n_tiles / R.tiles_x;
   const unsigned blocks = (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
   const unsigned threads = (unsigned)(64 * R.wx * R.wy);
+  const size_t lds = merge_lds_bytes(threads);
   if (R.mode == 0) {
-    if (R.counters) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(threads), 0, st, R);
-    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(threads), 0, st, R);
+    if (R.counters) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(threads), lds, st, R);
+    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(threads), lds, st, R);
   } else {
-    if (R.counters) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(threads), 0, st, R);
-    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(threads), 0, st, R);
+    if (R.counters) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(threads), lds, st, R);
+    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(threads), lds, st, R);
   }
   LS_HIP(hipGetLastError());
   return LS_OK;
@@ -919,7 +944,7 @@ int launch_render(const RenderArgs& R, hipStream_t st) {
 int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p, float* out,
                  RenderCounters* dev_counters, hipStream_t st) {
   RenderArgs R;
-  make_render_args(s, cam, p, out, 2, 2, dev_counters, &R);
+  make_render_args(s, cam, p, out, 1, 1, dev_counters, &R);
   return launch_render(R, st);
 }
 
@@ -938,12 +963,13 @@ int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_sta
                         const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
                         bool count, hipStream_t st) {
   const unsigned threads = (unsigned)(64 * plan.wx * plan.wy);
+  const size_t lds = merge_lds_bytes(threads);
   if (count)
-    hipLaunchKernelGGL((k_render_batch<true>), dim3(plan.blocks), dim3(threads), 0, st, dev_views,
-                       dev_tile_start, n_views, q, dev_queue);
+    hipLaunchKernelGGL((k_render_batch<true>), dim3(plan.blocks), dim3(threads), lds, st,
+                       dev_views, dev_tile_start, n_views, q, dev_queue);
   else
-    hipLaunchKernelGGL((k_render_batch<false>), dim3(plan.blocks), dim3(threads), 0, st, dev_views,
-                       dev_tile_start, n_views, q, dev_queue);
+    hipLaunchKernelGGL((k_render_batch<false>), dim3(plan.blocks), dim3(threads), lds, st,
+                       dev_views, dev_tile_start, n_views, q, dev_queue);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -951,7 +977,8 @@ int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_sta
 int batch_blocks_per_cu(int wx, int wy, int* out) {
   int n = 0;
   LS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_render_batch<false>,
-                                                      64 * wx * wy, 0));
+                                                      64 * wx * wy,
+                                                      merge_lds_bytes(64u * wx * wy)));
   *out = n > 0 ? n : 1;
   return LS_OK;
 }

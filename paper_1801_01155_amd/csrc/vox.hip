@@ -71,10 +71,11 @@ __device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
 constexpr int kErrOffsets = 1;
 constexpr int kErrRange = 2;
 
-// floor(num / den) for 0 <= num < 2^31, 0 < den < 2^31, without an integer
-// divide: fp64 quotient, corrected by one step either way.
-__device__ inline int64_t floor_div_pos(int64_t num, int64_t den) {
-  int64_t q = (int64_t)((double)num / (double)den);
+// floor(num / den) for 0 <= num <= 2^30, 0 < den, quotient at most 256: an
+// fp32 estimate (relative error below 1e-6, so off by at most one) corrected
+// by one exact integer step either way.
+__device__ inline int64_t floor_div_small(int64_t num, int64_t den) {
+  int64_t q = (int64_t)((float)num * __builtin_amdgcn_rcpf((float)den));
   if (q * den > num) --q;
   else if ((q + 1) * den <= num) ++q;
   return q;
@@ -89,8 +90,8 @@ __device__ inline uint32_t face_code(int axis, int side, const int64_t xn[3], in
   const int64_t step = den << ga.bin_shift;  // den * 256 / N
   int64_t lu = xn[ua] - ((int64_t)cell[ua] << 8) * den;
   int64_t lw = xn[wa] - ((int64_t)cell[wa] << 8) * den;
-  int64_t bu = floor_div_pos(lu, step);
-  int64_t bw = floor_div_pos(lw, step);
+  int64_t bu = floor_div_small(lu, step);
+  int64_t bw = floor_div_small(lw, step);
   bu = bu < ga.bins - 1 ? bu : ga.bins - 1;
   bw = bw < ga.bins - 1 ? bw : ga.bins - 1;
   return (uint32_t)(2 * axis + side) | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
@@ -145,14 +146,16 @@ __global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_
 struct Ev {
   int64_t xn[3];
   int64_t den;
-  uint32_t exit_code, entry_code;
+  uint32_t exit_code, entry_code;   // set when face codes are requested
+  int fa, exit_side;                // face axis, side of the exited voxel's face
+  int32_t ncell[3];                 // the entered voxel
 };
 
 // Enumerates the events of segment P0 -> P1 in order: crossings of the
 // planes x_a = 256 k (up iff P0_a < 256k <= P1_a, down iff P1_a < 256k <=
 // P0_a), ordered by their exact parameter; equal parameters are one event
 // whose face is the lowest axis's. f(ev, cell_before) per event.
-template <typename F>
+template <bool kCodes, typename F>
 __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], const GridArgs& ga,
                                       F&& f) {
   int64_t d[3], k[3];
@@ -196,8 +199,14 @@ __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], 
 #pragma unroll
     for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + nf * d[b];
     const int exit_side = (fa == 0 ? sg[0] : (fa == 1 ? sg[1] : sg[2])) > 0 ? 1 : 0;
-    ev.exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
-    ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
+    ev.fa = fa;
+    ev.exit_side = exit_side;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) ev.ncell[b] = ncell[b];
+    if (kCodes) {
+      ev.exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
+      ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
+    }
     f(ev, cell);
     any = false;
 #pragma unroll
@@ -219,14 +228,14 @@ struct Last {
   unsigned entry;
 };
 
-__device__ inline Last shfl_up_last(const Last& v, int d) {
+__device__ inline Last shfl_last(const Last& v, int src) {
   Last o;
-  o.has = __shfl_up(v.has, d, 64);
-  o.xn0 = __shfl_up(v.xn0, d, 64);
-  o.xn1 = __shfl_up(v.xn1, d, 64);
-  o.xn2 = __shfl_up(v.xn2, d, 64);
-  o.den = __shfl_up(v.den, d, 64);
-  o.entry = __shfl_up(v.entry, d, 64);
+  o.has = __shfl(v.has, src, 64);
+  o.xn0 = __shfl(v.xn0, src, 64);
+  o.xn1 = __shfl(v.xn1, src, 64);
+  o.xn2 = __shfl(v.xn2, src, 64);
+  o.den = __shfl(v.den, src, 64);
+  o.entry = __shfl(v.entry, src, 64);
   return o;
 }
 
@@ -261,19 +270,25 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t
       load_vertex<kFloatIn>(xyz, lat, i, sa, P0);
       load_vertex<kFloatIn>(xyz, lat, i + 1, sa, P1);
     }
-    // pass 1: number of events and the last one
+    // pass 1: number of events and the last one (face codes only for the last)
     uint32_t e = 0;
     Last mine{0, 0, 0, 0, 1, 0u};
-    if (valid)
-      for_each_event(P0, P1, ga, [&](const Ev& ev, const int32_t*) {
+    if (valid) {
+      Ev lastev{};
+      for_each_event<false>(P0, P1, ga, [&](const Ev& ev, const int32_t*) {
         ++e;
-        mine.has = 1;
-        mine.xn0 = ev.xn[0];
-        mine.xn1 = ev.xn[1];
-        mine.xn2 = ev.xn[2];
-        mine.den = ev.den;
-        mine.entry = ev.entry_code;
+        lastev = ev;
       });
+      if (e > 0) {
+        mine.has = 1;
+        mine.xn0 = lastev.xn[0];
+        mine.xn1 = lastev.xn[1];
+        mine.xn2 = lastev.xn[2];
+        mine.den = lastev.den;
+        mine.entry = face_code(lastev.fa, 1 - lastev.exit_side, lastev.xn, lastev.den,
+                               lastev.ncell, ga);
+      }
+    }
     // exclusive prefix sum of the event counts
     uint32_t inc = e;
 #pragma unroll
@@ -283,20 +298,23 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t
     }
     const uint32_t base = inc - e;
     const uint32_t total = __shfl(inc, 63, 64);
-    // inclusive "last event so far" scan, then shift by one lane
-    Last acc = mine;
+    // latest lane at or before this one with an event (max scan), then the
+    // last event strictly before this lane is that lane's of lane - 1
+    int src = mine.has ? lane : -1;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const Last o = shfl_up_last(acc, d);
-      if (lane >= d && !acc.has) acc = o;
+      const int o = __shfl_up(src, d, 64);
+      if (lane >= d) src = o > src ? o : src;
     }
-    Last before = shfl_up_last(acc, 1);
-    if (lane == 0 || !before.has) before = carry;
+    int prev_src = __shfl_up(src, 1, 64);
+    if (lane == 0) prev_src = -1;
+    Last before = shfl_last(mine, prev_src >= 0 ? prev_src : 0);
+    if (prev_src < 0) before = carry;
     // pass 2: emit the lines ending at this segment's events
     if (valid && e > 0) {
       uint64_t g = g0 + base;
       Last prev = before;
-      for_each_event(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
+      for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
         if (prev.has) {
           const uint64_t w = w0 + (g - 1);
           if (w < w_end) {
@@ -323,14 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t
       });
     }
     // carry the chunk's last event
-    Last last;
-    last.has = __shfl(acc.has, 63, 64);
-    last.xn0 = __shfl(acc.xn0, 63, 64);
-    last.xn1 = __shfl(acc.xn1, 63, 64);
-    last.xn2 = __shfl(acc.xn2, 63, 64);
-    last.den = __shfl(acc.den, 63, 64);
-    last.entry = __shfl(acc.entry, 63, 64);
-    if (last.has) carry = last;
+    const int last_src = __shfl(src, 63, 64);
+    if (last_src >= 0) carry = shfl_last(mine, last_src);
     g0 += total;
   }
   // slots past the curve's last line
@@ -348,17 +360,42 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const u
 }
 
 // Each CSR slot p holds some emitted line e of voxel v; its final position is
-// offsets[v] + (number of lines of v emitted before e).
+// offsets[v] + (number of lines of v emitted before e). A block handles 256
+// consecutive slots; the lists overlapping them (slots are grouped by voxel,
+// so they span [lo of the first slot's voxel, hi of the last's)) are staged
+// in LDS when they fit, else counted from memory.
+constexpr int kRankLds = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint32_t* vox,
                                                  const uint64_t* rec, int64_t n_records,
                                                  const uint32_t* offsets, uint64_t* records) {
-  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ uint32_t s_idx[kRankLds];
+  __shared__ uint32_t s_range[2];
+  const int64_t p0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t p = p0 + threadIdx.x;
+  const int64_t n_here = n_records - p0 < kBlock ? n_records - p0 : kBlock;
+  uint32_t e = 0, lo = 0, hi = 0;
+  if (p < n_records) {
+    e = idx[p];
+    const uint32_t v = vox[e];
+    lo = offsets[v];
+    hi = offsets[v + 1];
+  }
+  if (threadIdx.x == 0) s_range[0] = lo;
+  if ((int64_t)threadIdx.x == n_here - 1) s_range[1] = hi;
+  __syncthreads();
+  const uint32_t blo = s_range[0], bhi = s_range[1];
+  const bool staged = bhi - blo <= (uint32_t)kRankLds;   // block-uniform
+  if (staged)
+    for (uint32_t q = blo + threadIdx.x; q < bhi; q += kBlock) s_idx[q - blo] = idx[q];
+  __syncthreads();
   if (p >= n_records) return;
-  uint32_t e = idx[p];
-  uint32_t v = vox[e];
-  uint32_t lo = offsets[v], hi = offsets[v + 1];
   uint32_t r = 0;
-  for (uint32_t q = lo; q < hi; ++q) r += idx[q] < e;
+  if (staged) {
+    for (uint32_t q = lo; q < hi; ++q) r += s_idx[q - blo] < e;
+  } else {
+    for (uint32_t q = lo; q < hi; ++q) r += idx[q] < e;
+  }
   records[lo + r] = rec[e];
 }
 
@@ -467,20 +504,21 @@ inline unsigned curve_blocks(int64_t n) {
   return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
+// Temporary device buffer from the memory cache; released after the stream
+// it was used on has drained.
 struct DeviceBuf {
   void* p = nullptr;
+  hipStream_t st = nullptr;
+  explicit DeviceBuf(hipStream_t s) : st(s) {}
+  DeviceBuf(const DeviceBuf&) = delete;
+  DeviceBuf& operator=(const DeviceBuf&) = delete;
   ~DeviceBuf() {
-    if (p) (void)hipFree(p);
-  }
-  int alloc(size_t bytes) {
-    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      ls_set_error("device allocation of %zu bytes failed", bytes);
-      return LS_ENOMEM;
+    if (p) {
+      (void)hipStreamSynchronize(st);
+      pool_free(p);
     }
-    return LS_OK;
   }
+  int alloc(size_t bytes) { return pool_alloc(bytes, &p, nullptr); }
   template <typename T>
   T* as() { return static_cast<T*>(p); }
 };
@@ -495,7 +533,7 @@ int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream
   if (nv <= 0) return LS_OK;
   int64_t blocks = (nv + kBlock - 1) / kBlock;
   if (blocks > 1024) blocks = 1024;
-  DeviceBuf part, bad;
+  DeviceBuf part(st), bad(st);
   int rc;
   if ((rc = part.alloc(sizeof(double) * 6 * blocks)) || (rc = bad.alloc(sizeof(int)))) return rc;
   LS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
@@ -556,7 +594,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   int rc;
 
   // 1. per-curve slot counts + validation
-  DeviceBuf slots, err, sums64;
+  DeviceBuf slots(st), err(st), sums64(st);
   if ((rc = slots.alloc(sizeof(uint64_t) * (C + 1))) || (rc = err.alloc(sizeof(int))) ||
       (rc = sums64.alloc(sizeof(uint64_t) * scan_block_sums_len(C))))
     return rc;
@@ -598,7 +636,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   if ((rc = fill_u32(s->offsets, 0u, s->nvox + 1, st))) return rc;
 
   // 3. emit
-  DeviceBuf rec, vox, rank, sums32;
+  DeviceBuf rec(st), vox(st), rank(st), sums32(st);
   if ((rc = rec.alloc(sizeof(uint64_t) * n_slots)) || (rc = vox.alloc(sizeof(uint32_t) * n_slots)) ||
       (rc = rank.alloc(sizeof(uint32_t) * n_slots)) ||
       (rc = sums32.alloc(sizeof(uint32_t) * scan_block_sums_len(s->nvox))))
@@ -625,7 +663,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
 
   // 5. scatter + rank/gather into the set's record array
   if ((rc = ls_alloc(s, (void**)&s->records, sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
-  DeviceBuf idx;
+  DeviceBuf idx(st);
   if ((rc = idx.alloc(sizeof(uint32_t) * (n_rec ? n_rec : 1)))) return rc;
   if (n_slots > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for((int64_t)n_slots)), dim3(kBlock), 0, st,
@@ -641,7 +679,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   }
 
   // 6. list statistics and macro-cell occupancy
-  DeviceBuf stats;
+  DeviceBuf stats(st);
   if ((rc = stats.alloc(16))) return rc;
   LS_HIP(hipMemsetAsync(stats.p, 0, 16, st));
   const unsigned stat_blocks = std::min<unsigned>(blocks_for(s->nvox), 2048u);

@@ -104,21 +104,55 @@ def test_lod_pyramid_parity():
     assert s.info().n_levels == len(dims)
 
 
-def test_illumination_grids_parity():
-    ls, ref, s = _lod_case(grid=40, n=800)
+@pytest.mark.parametrize("grid,aperture", [(40, 1.0), ((37, 20, 29), 1.0), (40, 0.5)])
+def test_illumination_grids_parity(grid, aperture):
+    # cubic and ragged grids (partial 8^3 tiles); aperture 0.5 puts several
+    # samples on one level and gives the shadow cone a schedule whose LDS
+    # boxes exceed the tiled kernel's budget (untiled kernel)
+    ls, ref, s = _lod_case(grid=grid, n=800)
     lut = synth.lut_importance_alpha()
     light = synth.LIGHT_DIR
     L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, ao_cones=16, ao_radius=15.0,
-                        build_shadow=True, light_dir=light)
+                        cone_aperture=aperture, build_shadow=True, light_dir=light)
     torch.cuda.synchronize()
-    _, _, rho, _, _ = O.lod(ref, 40, 32, lut, opaque=False)
-    ao = O.ao_grid(rho, 40, 16, 15.0, 1.0)
-    sh = O.shadow_grid(rho, 40, np.array(light, dtype=np.float32).astype(np.float64))
+    _, _, rho, _, _ = O.lod(ref, grid, 32, lut, opaque=False)
+    ao = O.ao_grid(rho, grid, 16, 15.0, aperture)
+    sh = O.shadow_grid(rho, grid, np.array(light, dtype=np.float32).astype(np.float64), aperture)
     gao = L.lineset_export(s, L.EXPORT_AO).cpu().numpy()
     gsh = L.lineset_export(s, L.EXPORT_SHADOW).cpu().numpy()
-    print(f"[illum] ao max_abs_err={np.abs(gao - ao).max():.3e} "
+    print(f"[illum grid={grid} aperture={aperture}] ao max_abs_err={np.abs(gao - ao).max():.3e} "
           f"sh max_abs_err={np.abs(gsh - sh).max():.3e} ao_min={ao.min():.3f} sh_min={sh.min():.3f}",
           flush=True)
     assert ao.min() < 0.95 and sh.min() < 0.95
     assert np.abs(gao - ao).max() < 1e-5
     assert np.abs(gsh - sh).max() < 1e-5
+
+
+def test_memory_cache_reuse_and_trim():
+    """Set buffers and voxelizer temporaries come from the device memory
+    cache: a destroyed set's blocks are reused (stale contents must not leak
+    into the next CSR) and trimming returns them."""
+    dev = torch.cuda.current_device()
+    ls = synth.abc_lineset(4000, 200, 12, perturb=True)
+    ref, _ = U.oracle_csr_from_xyz(ls, 96, 32)
+    other = synth.abc_lineset(3000, 150, 13, perturb=True)
+    ref2, _ = U.oracle_csr_from_xyz(other, 96, 32)
+    a = L.lineset_voxelize(ls.curve_off, 96, 32, xyz=ls.xyz, attr=ls.attr)
+    _csr_equal(a, ref, "cache first")
+    a.close()
+    st = L.lineset_pool_stats(dev)
+    assert st["cached_bytes"] > 0 and st["held_bytes"] >= st["cached_bytes"]
+    b = L.lineset_voxelize(other.curve_off, 96, 32, xyz=other.xyz, attr=other.attr)
+    _csr_equal(b, ref2, "cache reused by another set")
+    b.close()
+    held = L.lineset_pool_stats(dev)["held_bytes"]
+    c = L.lineset_voxelize(ls.curve_off, 96, 32, xyz=ls.xyz, attr=ls.attr)
+    _csr_equal(c, ref, "cache reused by the same shape")
+    assert L.lineset_pool_stats(dev)["held_bytes"] == held    # no new device memory
+    c.close()
+    L.lineset_pool_trim()
+    st = L.lineset_pool_stats(dev)
+    print(f"[pool] after trim {st}", flush=True)
+    assert st["cached_bytes"] == 0
+    with pytest.raises(L.LinesetError):
+        L.lineset_pool_stats(-1)
