@@ -152,13 +152,19 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, Sched S, 
 // (tile extent on l) + 2 m_l cells per axis, m_l = ceil(max s_k / 2^l) + 2
 // over the samples on l. The block first copies each level's box into LDS
 // (coordinates clamped to the level, which makes plain trilinear
-// interpolation of the copy the clamp-to-edge interpolation of the level),
-// then every sample reads its 8 taps from LDS. The per-sample arithmetic is
-// that of sample(); only the source of the taps differs.
+// interpolation of the copy the clamp-to-edge interpolation of the level).
+//
+// With the tile origin a multiple of 8 and every level at most 3, a sample's
+// lattice coordinate on axis a depends only on the cone, the sample and the
+// voxel's position p_a = v_a - t0_a in the tile: x = ((p_a mod 2^l) + 0.5 +
+// s u_a) 2^-l - 0.5 (the arithmetic of sample()). The block tabulates, per
+// (cone, sample, axis, p_a), the tap's offset in the box and the weight
+// frac(x); a sample then costs three table reads, eight tap reads and the
+// seven interpolations.
 constexpr int kTile = 8;
 constexpr int kTileThreads = 256;
-constexpr int kTileSlots = 16;
-constexpr int kTileLdsFloats = 12288;   // 48 KB
+constexpr int kTileSlots = 4;            // levels 0..3
+constexpr int kTileLdsBytes = 49152;
 
 struct TileLevels {
   int32_t n;                        // distinct levels of the schedule
@@ -167,39 +173,17 @@ struct TileLevels {
   int32_t sz[kTileSlots];           // box edge, cells
   int32_t base[kTileSlots + 1];     // LDS offset (floats) of each box; base[n] = total
   int32_t slot[kMaxSamples];        // box of each sample
+  int32_t table;                    // LDS offset (floats, even) of the tap tables
   int32_t tiles[3];
   int32_t tiles_per_xcd;
 };
 
-__device__ inline float sample_lds(const float* __restrict__ lds, const TileLevels& TL, int q,
-                                   int lv, const int32_t v[3], const int32_t t0[3],
-                                   const float f[3]) {
-  const float scale = __builtin_ldexpf(1.0f, -lv);
-  const int32_t mask = (1 << lv) - 1;
-  const int sz = TL.sz[q];
-  int32_t li[3];
-  float fr[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float x = ((float)(v[a] & mask) + f[a]) * scale - 0.5f;
-    const float fl = floorf(x);
-    fr[a] = x - fl;
-    const int32_t i0 = (v[a] >> lv) + (int32_t)fl;
-    li[a] = min(max(i0 - ((t0[a] >> lv) - TL.m[q]), 0), sz - 2);
-  }
-  const float* b = lds + TL.base[q] + (li[2] * sz + li[1]) * sz + li[0];
-  const int sy = sz, sz2 = sz * sz;
-  const float* rows[4] = {b, b + sy, b + sz2, b + sz2 + sy};
-  float c[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c[k] = rows[k][0] + fr[0] * (rows[k][1] - rows[k][0]);
-  const float c0 = c[0] * (1.f - fr[1]) + c[1] * fr[1];
-  const float c1 = c[2] * (1.f - fr[1]) + c[3] * fr[1];
-  return c0 * (1.f - fr[2]) + c1 * fr[2];
-}
+// Tap offset (in floats, within the sample's box) and weight of one axis.
+struct Tap {
+  int32_t off;
+  float w;
+};
 
-// out[v] = 1 - (mean over the cones of the occlusion), for AO (n cones) and
-// the shadow grid (one cone toward the light).
 __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C, Sched S,
                                                               TileLevels TL, float* out) {
   extern __shared__ float lds[];
@@ -226,32 +210,56 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
       box[i] = r[(z * dy + y) * dx + x];
     }
   }
+  // tap tables: entry ((c * S.n + k) * 3 + a) * 8 + p
+  Tap* tab = reinterpret_cast<Tap*>(lds + TL.table);
+  const int n_tab = C.n * S.n * 24;
+  for (int e = threadIdx.x; e < n_tab; e += kTileThreads) {
+    const int p = e & 7, a = (e >> 3) % 3, ck = e / 24;
+    const int c = ck / S.n, k = ck % S.n;
+    const int q = TL.slot[k], lv = S.lv[k], sz = TL.sz[q];
+    const float u = (float)C.dir[c][a];
+    const float f = 0.5f + S.s[k] * u;
+    const float x = ((float)(p & ((1 << lv) - 1)) + f) * __builtin_ldexpf(1.0f, -lv) - 0.5f;
+    const float fl = floorf(x);
+    const int32_t li = min(max((p >> lv) + (int32_t)fl + TL.m[q], 0), sz - 2);
+    const int32_t stride = a == 0 ? 1 : (a == 1 ? sz : sz * sz);
+    tab[e] = Tap{li * stride, x - fl};
+  }
   __syncthreads();
   const float inv_n = 1.f / (float)C.n;
 #pragma unroll 1
   for (int half = 0; half < kTile * kTile * kTile / kTileThreads; ++half) {
     const int loc = threadIdx.x + half * kTileThreads;
-    const int32_t v[3] = {t0[0] + (loc & 7), t0[1] + ((loc >> 3) & 7), t0[2] + (loc >> 6)};
+    const int32_t pl[3] = {loc & 7, (loc >> 3) & 7, loc >> 6};
+    const int32_t v[3] = {t0[0] + pl[0], t0[1] + pl[1], t0[2] + pl[2]};
     if (v[0] >= P.g[0] || v[1] >= P.g[1] || v[2] >= P.g[2]) continue;
     const bool near_face = near_any_face(P, v, S.reach);
     float sum = 0.f;
-    for (int c = 0; c < C.n; ++c) {
-      const double* u = C.dir[c];
-      const float u32[3] = {(float)u[0], (float)u[1], (float)u[2]};
+    const Tap* tc = tab;
+    for (int c = 0; c < C.n; ++c, tc += 24 * S.n) {
       float occ = 0.f;
       for (int k = 0; k < S.n; ++k) {
-        const float s = S.s[k];
         if (near_face) {
+          const double s = (double)S.s[k];
           bool inside = true;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            const double x = ((double)v[a] + 0.5) + (double)s * u[a];
+            const double x = ((double)v[a] + 0.5) + s * C.dir[c][a];
             inside &= x >= 0.0 && x < (double)P.g[a];
           }
           if (!inside) break;
         }
-        const float f[3] = {0.5f + s * u32[0], 0.5f + s * u32[1], 0.5f + s * u32[2]};
-        occ += sample_lds(lds, TL, TL.slot[k], S.lv[k], v, t0, f) * S.D[k];
+        const Tap* tk = tc + 24 * k;
+        const Tap ex = tk[pl[0]], ey = tk[8 + pl[1]], ez = tk[16 + pl[2]];
+        const int q = TL.slot[k], sz = TL.sz[q], sz2 = sz * sz;
+        const float* bp = lds + TL.base[q] + ex.off + ey.off + ez.off;
+        const float c00 = bp[0] + ex.w * (bp[1] - bp[0]);
+        const float c10 = bp[sz] + ex.w * (bp[sz + 1] - bp[sz]);
+        const float c01 = bp[sz2] + ex.w * (bp[sz2 + 1] - bp[sz2]);
+        const float c11 = bp[sz2 + sz] + ex.w * (bp[sz2 + sz + 1] - bp[sz2 + sz]);
+        const float c0 = c00 + ey.w * (c10 - c00);
+        const float c1 = c01 + ey.w * (c11 - c01);
+        occ += (c0 + ez.w * (c1 - c0)) * S.D[k];
         if (occ >= 1.f) break;
       }
       sum += occ < 1.f ? occ : 1.f;
@@ -302,16 +310,17 @@ Pyramid make_pyramid(const ls_lineset* s) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Boxes of the tiled kernel for schedule S; false if they exceed the LDS
-// budget (then the untiled kernels run).
-bool make_tile_levels(const ls_lineset* s, const Sched& S, TileLevels* T) {
+// Boxes and tap tables of the tiled kernel for schedule S and n_cones cones;
+// false if a level above 3 is sampled or LDS would exceed the budget (then
+// the untiled kernels run).
+bool make_tile_levels(const ls_lineset* s, const Sched& S, int n_cones, TileLevels* T) {
   *T = TileLevels{};
   for (int k = 0; k < S.n; ++k) {
     const int lv = S.lv[k];
+    if (lv > 3) return false;
     int q = 0;
     while (q < T->n && T->lv[q] != lv) ++q;
     if (q == T->n) {
-      if (T->n == kTileSlots) return false;
       T->lv[q] = lv;
       T->m[q] = 0;
       T->n++;
@@ -326,13 +335,21 @@ bool make_tile_levels(const ls_lineset* s, const Sched& S, TileLevels* T) {
     T->sz[q] = ext + 2 * T->m[q];
     T->base[q] = (int32_t)total;
     total += (int64_t)T->sz[q] * T->sz[q] * T->sz[q];
-    if (total > kTileLdsFloats) return false;
   }
   T->base[T->n] = (int32_t)total;
+  total += total & 1;                          // 8-byte alignment of the tables
+  T->table = (int32_t)total;
+  total += (int64_t)n_cones * S.n * 24 * 2;    // Tap = 2 floats
+  if (total * 4 > kTileLdsBytes) return false;
   for (int a = 0; a < 3; ++a) T->tiles[a] = (s->grid[a] + kTile - 1) / kTile;
   const int64_t nt = (int64_t)T->tiles[0] * T->tiles[1] * T->tiles[2];
   T->tiles_per_xcd = (int32_t)((nt + 7) / 8);
   return true;
+}
+
+// LDS bytes of the tiled kernel's plan T.
+size_t tile_lds_bytes(const TileLevels& T, int n_cones, int n_samples) {
+  return sizeof(float) * ((size_t)T.table + (size_t)n_cones * n_samples * 24 * 2);
 }
 
 int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
@@ -340,8 +357,8 @@ int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out
   // the tiled kernel pays one LDS fill per tile; with few samples per voxel
   // (the single shadow cone) direct gathers are cheaper
   TileLevels T;
-  if (C.n >= 4 && make_tile_levels(s, S, &T)) {
-    const size_t lds = sizeof(float) * (size_t)T.base[T.n];
+  if (C.n >= 4 && make_tile_levels(s, S, C.n, &T)) {
+    const size_t lds = tile_lds_bytes(T, C.n, S.n);
     hipLaunchKernelGGL(k_cones_tiled, dim3((unsigned)(8 * T.tiles_per_xcd)), dim3(kTileThreads),
                        lds, st, make_pyramid(s), C, S, T, out);
   } else if (ao) {

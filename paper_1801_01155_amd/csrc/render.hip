@@ -19,7 +19,9 @@
 //     an empty 4^3 macro cell (one 64-bit occupancy word) is crossed in one
 //     step;
 //  3. per non-empty voxel, capsule tests in fp32 in a voxel-local frame
-//     (origin = ray point at t0 minus the voxel corner, formed in fp64);
+//     (origin = ray point at t0 minus the voxel corner, formed in fp64); in
+//     own-list mode the lists of all lanes that entered a non-empty voxel in
+//     the same step are tested by the whole wave together (voxels_coop);
 //  4. accepted hits go into a 4-slot register-resident sorted buffer keyed
 //     by (entry t, record index); a voxel with more hits is swept again for
 //     the next 4;
@@ -32,6 +34,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSortSlots = 4;
+constexpr int kStage = 4;       // records of a list loaded together
 constexpr int kMergeSlots = 8;
 constexpr int kXcds = 8;
 
@@ -517,20 +520,26 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
   if (R.opaque) {
     float best = INFINITY;
     uint32_t bi = 0xFFFFFFFFu;
-    // the next record's load is issued before the current test (one-deep prefetch)
-    uint64_t next = R.records[lo];
-    for (uint32_t k = lo; k < hi; ++k) {
-      const uint64_t rec = next;
-      if (k + 1 < hi) next = R.records[k + 1];
-      float a[3], b[3], si, so;
-      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-      cnt.tested++;
-      if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && vt0 + (double)si >= 0.0) {
-        cnt.hits++;
-        if (si < best || (si == best && k < bi)) {
-          best = si;
-          bi = k;
+    // records are loaded kStage at a time, all loads in flight together
+    for (uint32_t k0 = lo; k0 < hi; k0 += kStage) {
+      uint64_t st[kStage];
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) st[j] = k0 + j < hi ? R.records[k0 + j] : 0ull;
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        const uint32_t k = k0 + j;
+        if (k >= hi) break;
+        const uint64_t rec = st[j];
+        float a[3], b[3], si, so;
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+        cnt.tested++;
+        if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && vt0 + (double)si >= 0.0) {
+          cnt.hits++;
+          if (si < best || (si == best && k < bi)) {
+            best = si;
+            bi = k;
+          }
         }
       }
     }
@@ -552,19 +561,25 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
   bool first = true;
   for (;;) {
     HitBuf<float> buf;
-    uint64_t next = R.records[lo];
-    for (uint32_t k = lo; k < hi; ++k) {
-      const uint64_t rec = next;
-      if (k + 1 < hi) next = R.records[k + 1];
-      float a[3], b[3], si, so;
-      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-      cnt.tested++;
-      if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
-      if (!(vt0 + (double)si >= 0.0)) continue;
-      if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
-      if (first) cnt.hits++;
-      buf.insert(si, so, k, 0u, rec);
+    for (uint32_t k0 = lo; k0 < hi; k0 += kStage) {
+      uint64_t st[kStage];
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) st[j] = k0 + j < hi ? R.records[k0 + j] : 0ull;
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        const uint32_t k = k0 + j;
+        if (k >= hi) break;
+        const uint64_t rec = st[j];
+        float a[3], b[3], si, so;
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+        cnt.tested++;
+        if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
+        if (!(vt0 + (double)si >= 0.0)) continue;
+        if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
+        if (first) cnt.hits++;
+        buf.insert(si, so, k, 0u, rec);
+      }
     }
     cnt.list_bytes += 8u * (hi - lo);
     // the pass's last key bounds the next pass (read before consuming)
@@ -589,6 +604,198 @@ __device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArg
     if (acc.done || !more) break;
     first = false;
     cnt.passes++;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-cooperative list tests (own-list mode). In one step of the grid walk
+// only some lanes stand in a non-empty voxel, and their lists differ in
+// length; testing each lane's own list leaves most lanes idle while the
+// longest list is tested. Instead the (ray, line) pairs of the whole wave are
+// numbered by a prefix sum over the list lengths and dealt out 64 at a time:
+// pair w belongs to the last lane r with P_r <= w (a binary search over the
+// lanes' prefixes), and the tester reads r's ray frame by cross-lane reads.
+// Hits go back to their owners through a ballot: owner r pulls the hits of
+// the testers in its pair range one by one, so every owner sees the same set
+// of hits (and the same sorted buffer) as if it had tested its list itself.
+__device__ inline int wave_lane() { return (int)(threadIdx.x & 63); }
+
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+  const int lane = wave_lane();
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+// Last lane r with P_r <= w (P non-decreasing over the lanes).
+__device__ inline int pair_owner(uint32_t P, uint32_t w) {
+  int r = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1) {
+    const uint32_t pc = __shfl(P, r + step, 64);
+    if (pc <= w) r += step;
+  }
+  return r;
+}
+
+// Bits [a, b) of a 64-bit mask (0 <= a <= b <= 64).
+__device__ inline unsigned long long bit_range(int a, int b) {
+  if (a >= b) return 0ull;
+  const unsigned long long hi = b >= 64 ? ~0ull : ((1ull << b) - 1ull);
+  return hi & ~((1ull << a) - 1ull);
+}
+
+__device__ inline double shfl_f64(double v, int src) {
+  return __hiloint2double(__shfl(__double2hiint(v), src, 64), __shfl(__double2loint(v), src, 64));
+}
+
+// Called by all 64 lanes together. Lane `mine` owns the voxel vcell entered
+// at vt0 with lines [lo, hi).
+__device__ __attribute__((always_inline)) inline void voxels_coop(
+    const RenderArgs& R, const float4* lut_lds, const Ray& ray, const int32_t vcell[3],
+    double vt0, const Shade& S, float dd, float inv_dd, bool mine, uint32_t lo, uint32_t hi,
+    Accum& acc, Counts& cnt) {
+  const int lane = wave_lane();
+  const uint32_t n = mine ? hi - lo : 0u;
+  if (__ballot(n != 0u) == 0ull) return;
+  float q[3] = {0.f, 0.f, 0.f};
+  if (mine) local_origin(ray, vt0, vcell, q);
+  if (R.opaque) {
+    uint32_t N;
+    const uint32_t P = wave_excl_scan(n, N);
+    float best = INFINITY;
+    uint32_t bi = 0xFFFFFFFFu;
+    for (uint32_t base = 0; base < N; base += 64) {
+      const uint32_t w = base + (uint32_t)lane;
+      const int r = pair_owner(P, w);
+      const float qr[3] = {__shfl(q[0], r, 64), __shfl(q[1], r, 64), __shfl(q[2], r, 64)};
+      const float dr[3] = {__shfl(ray.d[0], r, 64), __shfl(ray.d[1], r, 64),
+                           __shfl(ray.d[2], r, 64)};
+      const float ddr = __shfl(dd, r, 64), iddr = __shfl(inv_dd, r, 64);
+      const uint32_t lor = __shfl(lo, r, 64), Pr = __shfl(P, r, 64);
+      const double vt0r = shfl_f64(vt0, r);
+      bool hit = false;
+      float si = 0.f, so = 0.f;
+      uint32_t k = 0;
+      if (w < N) {
+        k = lor + (w - Pr);
+        const uint64_t rec = R.records[k];
+        float a[3], b[3];
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+        cnt.tested++;
+        hit = capsule(qr, dr, ddr, iddr, a, b, R.r2, si, so) && vt0r + (double)si >= 0.0;
+      }
+      unsigned long long m =
+          __ballot(hit) & bit_range(max((int)P - (int)base, 0), min((int)(P + n) - (int)base, 64));
+      while (__ballot(m != 0ull) != 0ull) {
+        const int src = m ? __builtin_ctzll(m) : 0;
+        const float ts = __shfl(si, src, 64);
+        const uint32_t ks = __shfl(k, src, 64);
+        if (m) {
+          cnt.hits++;
+          if (ts < best || (ts == best && ks < bi)) {
+            best = ts;
+            bi = ks;
+          }
+          m &= m - 1ull;
+        }
+      }
+    }
+    if (mine) {
+      cnt.list_bytes += 8u * n;
+      if (bi != 0xFFFFFFFFu) {
+        const uint64_t rec = R.records[bi];
+        float a[3], b[3], p[3];
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
+        composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
+        acc.done = true;
+      }
+    }
+    return;
+  }
+  // transparent: passes of up to kSortSlots hits per owner, in (t, index) order
+  bool need = n != 0u;
+  bool first = true;
+  float last_t = -INFINITY;
+  uint32_t last_i = 0;
+  while (__ballot(need) != 0ull) {
+    const uint32_t np = need ? n : 0u;
+    uint32_t N;
+    const uint32_t P = wave_excl_scan(np, N);
+    HitBuf<float> buf;
+    for (uint32_t base = 0; base < N; base += 64) {
+      const uint32_t w = base + (uint32_t)lane;
+      const int r = pair_owner(P, w);
+      const float qr[3] = {__shfl(q[0], r, 64), __shfl(q[1], r, 64), __shfl(q[2], r, 64)};
+      const float dr[3] = {__shfl(ray.d[0], r, 64), __shfl(ray.d[1], r, 64),
+                           __shfl(ray.d[2], r, 64)};
+      const float ddr = __shfl(dd, r, 64), iddr = __shfl(inv_dd, r, 64);
+      const uint32_t lor = __shfl(lo, r, 64), Pr = __shfl(P, r, 64);
+      const double vt0r = shfl_f64(vt0, r);
+      const bool firstr = __shfl((int)first, r, 64) != 0;
+      const float ltr = __shfl(last_t, r, 64);
+      const uint32_t lir = __shfl(last_i, r, 64);
+      bool hit = false;
+      float si = 0.f, so = 0.f;
+      uint32_t k = 0;
+      if (w < N) {
+        k = lor + (w - Pr);
+        const uint64_t rec = R.records[k];
+        float a[3], b[3];
+        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
+        cnt.tested++;
+        // t >= 0 and the pass filter are applied here, so only kept hits are pulled
+        hit = capsule(qr, dr, ddr, iddr, a, b, R.r2, si, so) && vt0r + (double)si >= 0.0 &&
+              (firstr || HitBuf<float>::less(ltr, lir, si, k));
+      }
+      unsigned long long m =
+          __ballot(hit) & bit_range(max((int)P - (int)base, 0), min((int)(P + np) - (int)base, 64));
+      while (__ballot(m != 0ull) != 0ull) {
+        const int src = m ? __builtin_ctzll(m) : 0;
+        const float ts = __shfl(si, src, 64), os = __shfl(so, src, 64);
+        const uint32_t ks = __shfl(k, src, 64);
+        if (m) {
+          if (first) cnt.hits++;
+          buf.insert(ts, os, ks, 0u, 0ull);   // the record is reloaded when composited
+          m &= m - 1ull;
+        }
+      }
+    }
+    if (need) {
+      cnt.list_bytes += 8u * n;
+      // the pass's last key bounds the next pass (read before consuming)
+      last_t = buf.t[kSortSlots - 1];
+      last_i = buf.idx[kSortSlots - 1];
+      const bool more = buf.dropped != 0;
+      while (buf.n > 0 && !acc.done) {
+        const float t_in = buf.t[0], t_out = buf.so[0];
+        const uint64_t rc = R.records[buf.idx[0]];
+        buf.pop_front();
+        if (R.merge) {
+          const uint32_t tag = (uint32_t)(rc >> 40);
+          if (merge_hit(acc, tag, vt0 + (double)t_in, vt0 + (double)t_out, cnt)) continue;
+        }
+        float a[3], b[3], p[3];
+        decode_point((uint32_t)(rc & 0x7FFFu), R.inv_bins, a);
+        decode_point((uint32_t)((rc >> 15) & 0x7FFFu), R.inv_bins, b);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
+        composite(R, lut_lds, S, acc, rc, vcell, p, a, b, cnt);
+      }
+      need = more && !acc.done;
+      if (need) cnt.passes++;
+      first = false;
+    }
   }
 }
 
@@ -693,13 +900,17 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
 }
 
 template <int kMode>
+// All 64 lanes of the wave call this together (mode 0 tests lists
+// cooperatively); a lane whose pixel lies outside the image takes part
+// with a dead ray and writes nothing.
 __device__ __attribute__((always_inline)) inline void render_pixel(const RenderArgs& R, const float4* lut_lds, const MergeLds& mt, int i,
-                                                             int j, Counts& cnt) {
+                                                             int j, bool valid, Counts& cnt) {
   Ray ray;
-  make_ray(R, i, j, ray.o, ray.d);
+  make_ray(R, valid ? i : 0, valid ? j : 0, ray.o, ray.d);
   dda_init(R, ray);
+  if (!valid) ray.alive = false;
   Accum acc(mt);
-  if (ray.alive) {
+  {
     const float dd = dot3(ray.d, ray.d);
     const float inv_dd = 1.f / dd;
     const double idd = 1.0 / ((double)ray.d[0] * ray.d[0] + (double)ray.d[1] * ray.d[1] +
@@ -721,36 +932,48 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
     if (kMode == 0) {
       // One 64-bit occupancy word per 4^3 macro cell: an empty macro cell is
       // jumped in one step, and an empty voxel inside an occupied one is
-      // stepped over without touching the lists. (Deferring the list tests
-      // until every lane of the wave has reached a non-empty voxel was
-      // measured slower: the extra live state cost more than the divergence
-      // it removed.)
+      // stepped over without touching the lists. Each step, the lanes that
+      // entered a non-empty voxel test their lists together (voxels_coop).
       int64_t last_mid = -1;
       unsigned long long occ = 0;
-      for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
-        const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
-        const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
-        if (mid != last_mid) {
-          last_mid = mid;
-          occ = R.occ[mid];
-          cnt.list_bytes += 8u;
+      for (int it = 0;; ++it) {
+        const bool live = it < max_steps && ray.alive && !acc.done;
+        if (__ballot(live) == 0ull) break;
+        bool mine = false;
+        uint32_t lo = 0, hi = 0;
+        int32_t vc[3] = {0, 0, 0};
+        double vt0 = 0.0;
+        if (live) {
+          const int32_t m[3] = {ray.cell[0] >> 2, ray.cell[1] >> 2, ray.cell[2] >> 2};
+          const int64_t mid = m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2]);
+          if (mid != last_mid) {
+            last_mid = mid;
+            occ = R.occ[mid];
+            cnt.list_bytes += 8u;
+          }
+          if (occ == 0ull) {
+            cnt.skips++;
+            macro_jump(R, ray, m);
+          } else {
+            cnt.visited++;
+            const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
+            if ((occ >> bit) & 1ull) {
+              const int64_t vid =
+                  ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
+              lo = R.offsets[vid];
+              hi = R.offsets[vid + 1];
+              cnt.list_bytes += 8u;
+              cnt.nonempty++;
+              mine = true;
+              vc[0] = ray.cell[0];
+              vc[1] = ray.cell[1];
+              vc[2] = ray.cell[2];
+              vt0 = ray.t0;
+            }
+            ray.t0 = dda_step(R, ray);
+          }
         }
-        if (occ == 0ull) {
-          cnt.skips++;
-          macro_jump(R, ray, m);
-          continue;
-        }
-        cnt.visited++;
-        const int bit = (ray.cell[0] & 3) + 4 * (ray.cell[1] & 3) + 16 * (ray.cell[2] & 3);
-        if ((occ >> bit) & 1ull) {
-          const int64_t vid =
-              ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
-          const uint32_t lo = R.offsets[vid], hi = R.offsets[vid + 1];
-          cnt.list_bytes += 8u;
-          cnt.nonempty++;
-          voxel_fast(R, lut_lds, ray, ray.cell, ray.t0, S, dd, inv_dd, lo, hi, acc, cnt);
-        }
-        ray.t0 = dda_step(R, ray);
+        voxels_coop(R, lut_lds, ray, vc, vt0, S, dd, inv_dd, mine, lo, hi, acc, cnt);
       }
     } else {
       for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
@@ -763,8 +986,10 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
       }
     }
   }
-  float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
-  reinterpret_cast<float4*>(R.out)[(int64_t)j * R.W + i] = px;
+  if (valid) {
+    float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
+    reinterpret_cast<float4*>(R.out)[(int64_t)j * R.W + i] = px;
+  }
 }
 
 // Pixel of lane `lane` in wave `wave` of tile `tile` (tile = wx x wy waves of 8 x 8).
@@ -775,9 +1000,9 @@ __device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int l
 }
 
 __device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, const float4* lut_lds, const MergeLds& mt, int i, int j,
-                       Counts& cnt) {
-  if (R.mode == 0) render_pixel<0>(R, lut_lds, mt, i, j, cnt);
-  else render_pixel<1>(R, lut_lds, mt, i, j, cnt);
+                       bool valid, Counts& cnt) {
+  if (R.mode == 0) render_pixel<0>(R, lut_lds, mt, i, j, valid, cnt);
+  else render_pixel<1>(R, lut_lds, mt, i, j, valid, cnt);
 }
 
 // Stages a view's transfer function (256 RGBA) in LDS.
@@ -787,7 +1012,7 @@ __device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
 }
 
 template <int kMode, bool kCount>
-__global__ __launch_bounds__(kBlock, 4) void k_render(RenderArgs R) {
+__global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
   // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every XCD
   // gets a share of the part of the screen the grid covers.
@@ -808,7 +1033,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_render(RenderArgs R) {
   {
     int i, j;
     tile_pixel(R, tile, threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if (i < R.W && j < R.H) render_pixel<kMode>(R, lut_lds, merge_lds, i, j, cnt);
+    render_pixel<kMode>(R, lut_lds, merge_lds, i, j, i < R.W && j < R.H, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
@@ -872,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
     __syncthreads();
     int i, j;
     tile_pixel(R, t - tile_start[v], threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    if ((int)threadIdx.x < 64 * R.wx * R.wy && i < R.W && j < R.H) render_any(R, lut_lds, merge_lds, i, j, cnt);
+    render_any(R, lut_lds, merge_lds, i, j, i < R.W && j < R.H, cnt);
     __syncthreads();
   }
   if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);

@@ -246,7 +246,7 @@ __device__ inline Last shfl_last(const Last& v, int src) {
 // unused slots are marked invalid. Each line takes its rank in its voxel
 // with one atomic on the histogram.
 template <bool kFloatIn>
-__global__ __launch_bounds__(kBlock) void k_emit(const float* xyz, const int32_t* lat,
+__global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
                                                  int64_t n_curves, SnapArgs sa, GridArgs ga,
                                                  const uint64_t* slot_off, uint64_t* rec_out,
