@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrivals per rate: max(100, rate * seconds), capped")
     ap.add_argument("--serve-max-requests", type=int, default=2000)
-    ap.add_argument("--serve-inflight-mib", type=float, default=64.0,
+    ap.add_argument("--serve-inflight-mib", type=float, default=36.0,
                     help="HBM budget for outputs in flight, beyond the resident sets")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="append one 2 GiB device-to-device copy (the reference kernel "

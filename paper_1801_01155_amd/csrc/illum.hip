@@ -165,6 +165,7 @@ constexpr int kTile = 8;
 constexpr int kTileThreads = 256;
 constexpr int kTileSlots = 4;            // levels 0..3
 constexpr int kTileLdsBytes = 49152;
+constexpr int kTileMaxSamples = 8;       // instantiated schedule lengths
 
 struct TileLevels {
   int32_t n;                        // distinct levels of the schedule
@@ -184,6 +185,9 @@ struct Tap {
   float w;
 };
 
+// kN = S.n: the sample loop is unrolled, so the schedule's per-sample
+// constants (box, edge, weight) stay in scalar registers for the whole block.
+template <int kN>
 __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C, Sched S,
                                                               TileLevels TL, float* out) {
   extern __shared__ float lds[];
@@ -212,10 +216,10 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
   }
   // tap tables: entry ((c * S.n + k) * 3 + a) * 8 + p
   Tap* tab = reinterpret_cast<Tap*>(lds + TL.table);
-  const int n_tab = C.n * S.n * 24;
+  const int n_tab = C.n * kN * 24;
   for (int e = threadIdx.x; e < n_tab; e += kTileThreads) {
     const int p = e & 7, a = (e >> 3) % 3, ck = e / 24;
-    const int c = ck / S.n, k = ck % S.n;
+    const int c = ck / kN, k = ck % kN;
     const int q = TL.slot[k], lv = S.lv[k], sz = TL.sz[q];
     const float u = (float)C.dir[c][a];
     const float f = 0.5f + S.s[k] * u;
@@ -227,6 +231,17 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
   }
   __syncthreads();
   const float inv_n = 1.f / (float)C.n;
+  // per-sample constants, read once (wave-uniform, scalar registers)
+  int32_t kbase[kN], ksz[kN];
+  float kD[kN], ks[kN];
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    const int q = TL.slot[k];
+    kbase[k] = TL.base[q];
+    ksz[k] = TL.sz[q];
+    kD[k] = S.D[k];
+    ks[k] = S.s[k];
+  }
 #pragma unroll 1
   for (int half = 0; half < kTile * kTile * kTile / kTileThreads; ++half) {
     const int loc = threadIdx.x + half * kTileThreads;
@@ -236,31 +251,33 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
     const bool near_face = near_any_face(P, v, S.reach);
     float sum = 0.f;
     const Tap* tc = tab;
-    for (int c = 0; c < C.n; ++c, tc += 24 * S.n) {
+    for (int c = 0; c < C.n; ++c, tc += 24 * kN) {
       float occ = 0.f;
-      for (int k = 0; k < S.n; ++k) {
-        if (near_face) {
-          const double s = (double)S.s[k];
-          bool inside = true;
+      bool go = true;
+#pragma unroll
+      for (int k = 0; k < kN; ++k) {
+        if (go && near_face) {
+          const double s = (double)ks[k];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const double x = ((double)v[a] + 0.5) + s * C.dir[c][a];
-            inside &= x >= 0.0 && x < (double)P.g[a];
+            go &= x >= 0.0 && x < (double)P.g[a];
           }
-          if (!inside) break;
         }
-        const Tap* tk = tc + 24 * k;
-        const Tap ex = tk[pl[0]], ey = tk[8 + pl[1]], ez = tk[16 + pl[2]];
-        const int q = TL.slot[k], sz = TL.sz[q], sz2 = sz * sz;
-        const float* bp = lds + TL.base[q] + ex.off + ey.off + ez.off;
-        const float c00 = bp[0] + ex.w * (bp[1] - bp[0]);
-        const float c10 = bp[sz] + ex.w * (bp[sz + 1] - bp[sz]);
-        const float c01 = bp[sz2] + ex.w * (bp[sz2 + 1] - bp[sz2]);
-        const float c11 = bp[sz2 + sz] + ex.w * (bp[sz2 + sz + 1] - bp[sz2 + sz]);
-        const float c0 = c00 + ey.w * (c10 - c00);
-        const float c1 = c01 + ey.w * (c11 - c01);
-        occ += (c0 + ez.w * (c1 - c0)) * S.D[k];
-        if (occ >= 1.f) break;
+        if (go) {
+          const Tap* tk = tc + 24 * k;
+          const Tap ex = tk[pl[0]], ey = tk[8 + pl[1]], ez = tk[16 + pl[2]];
+          const int sz = ksz[k], sz2 = sz * sz;
+          const float* bp = lds + kbase[k] + ex.off + ey.off + ez.off;
+          const float c00 = bp[0] + ex.w * (bp[1] - bp[0]);
+          const float c10 = bp[sz] + ex.w * (bp[sz + 1] - bp[sz]);
+          const float c01 = bp[sz2] + ex.w * (bp[sz2 + 1] - bp[sz2]);
+          const float c11 = bp[sz2 + sz] + ex.w * (bp[sz2 + sz + 1] - bp[sz2 + sz]);
+          const float c0 = c00 + ey.w * (c10 - c00);
+          const float c1 = c01 + ey.w * (c11 - c01);
+          occ += (c0 + ez.w * (c1 - c0)) * kD[k];
+          go = occ < 1.f;
+        }
       }
       sum += occ < 1.f ? occ : 1.f;
     }
@@ -357,10 +374,17 @@ int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out
   // the tiled kernel pays one LDS fill per tile; with few samples per voxel
   // (the single shadow cone) direct gathers are cheaper
   TileLevels T;
-  if (C.n >= 4 && make_tile_levels(s, S, C.n, &T)) {
+  if (C.n >= 4 && S.n >= 1 && S.n <= kTileMaxSamples && make_tile_levels(s, S, C.n, &T)) {
     const size_t lds = tile_lds_bytes(T, C.n, S.n);
-    hipLaunchKernelGGL(k_cones_tiled, dim3((unsigned)(8 * T.tiles_per_xcd)), dim3(kTileThreads),
-                       lds, st, make_pyramid(s), C, S, T, out);
+    const dim3 grid((unsigned)(8 * T.tiles_per_xcd)), block(kTileThreads);
+    const Pyramid P = make_pyramid(s);
+    switch (S.n) {
+#define LS_CONES_CASE(N) \
+  case N: hipLaunchKernelGGL(k_cones_tiled<N>, grid, block, lds, st, P, C, S, T, out); break;
+      LS_CONES_CASE(1) LS_CONES_CASE(2) LS_CONES_CASE(3) LS_CONES_CASE(4)
+      LS_CONES_CASE(5) LS_CONES_CASE(6) LS_CONES_CASE(7) LS_CONES_CASE(8)
+#undef LS_CONES_CASE
+    }
   } else if (ao) {
     hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
                        S, s->nvox, out);
