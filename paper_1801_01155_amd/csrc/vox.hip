@@ -71,13 +71,13 @@ __device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
 constexpr int kErrOffsets = 1;
 constexpr int kErrRange = 2;
 
-// floor(num / den) for 0 <= num <= 2^30, 0 < den, quotient at most 256: an
+// floor(num / den) for 0 <= num <= 2^30, 0 < den < 2^31, quotient at most 256: an
 // fp32 estimate (relative error below 1e-6, so off by at most one) corrected
 // by one exact integer step either way.
-__device__ inline int64_t floor_div_small(int64_t num, int64_t den) {
-  int64_t q = (int64_t)((float)num * __builtin_amdgcn_rcpf((float)den));
-  if (q * den > num) --q;
-  else if ((q + 1) * den <= num) ++q;
+__device__ inline int32_t floor_div_small(int64_t num, int32_t den) {
+  int32_t q = (int32_t)((float)num * __builtin_amdgcn_rcpf((float)den));
+  if ((int64_t)q * den > num) --q;
+  else if ((int64_t)(q + 1) * den <= num) ++q;
   return q;
 }
 
@@ -85,13 +85,16 @@ __device__ inline int64_t floor_div_small(int64_t num, int64_t den) {
 // xn = event point * den (exact), local coordinate = xn - 256 cell den in [0, 256 den].
 __device__ inline uint32_t face_code(int axis, int side, const int64_t xn[3], int64_t den,
                                      const int32_t cell[3], const GridArgs& ga) {
-  const int ua = axis == 0 ? 1 : 0;
-  const int wa = axis == 2 ? 1 : 2;
-  const int64_t step = den << ga.bin_shift;  // den * 256 / N
-  int64_t lu = xn[ua] - ((int64_t)cell[ua] << 8) * den;
-  int64_t lw = xn[wa] - ((int64_t)cell[wa] << 8) * den;
-  int64_t bu = floor_div_small(lu, step);
-  int64_t bw = floor_div_small(lw, step);
+  const int64_t x_u = axis == 0 ? xn[1] : xn[0];
+  const int64_t x_w = axis == 2 ? xn[1] : xn[2];
+  const int32_t c_u = axis == 0 ? cell[1] : cell[0];
+  const int32_t c_w = axis == 2 ? cell[1] : cell[2];
+  const int32_t den32 = (int32_t)den;                 // below 2^18
+  const int32_t step = den32 << ga.bin_shift;         // den * 256 / N, below 2^26
+  const int64_t lu = x_u - (int64_t)(c_u << 8) * den32;
+  const int64_t lw = x_w - (int64_t)(c_w << 8) * den32;
+  int32_t bu = floor_div_small(lu, step);
+  int32_t bw = floor_div_small(lw, step);
   bu = bu < ga.bins - 1 ? bu : ga.bins - 1;
   bw = bw < ga.bins - 1 ? bw : ga.bins - 1;
   return (uint32_t)(2 * axis + side) | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
@@ -148,6 +151,7 @@ struct Ev {
   int64_t den;
   uint32_t exit_code, entry_code;   // set when face codes are requested
   int fa, exit_side;                // face axis, side of the exited voxel's face
+  int planes;                       // planes crossed at this event (1 to 3)
   int32_t ncell[3];                 // the entered voxel
 };
 
@@ -158,13 +162,15 @@ struct Ev {
 template <bool kCodes, typename F>
 __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], const GridArgs& ga,
                                       F&& f) {
-  int64_t d[3], k[3];
+  // lattice coordinates are below 2^18 (grid sides <= 1024), so plane
+  // offsets and differences fit 32 bits; products are formed in 64 bits
+  int32_t d[3], k[3];
   int32_t left[3], cell[3];
   int sg[3];
   bool any = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    d[a] = (int64_t)P1[a] - P0[a];
+    d[a] = P1[a] - P0[a];
     const int32_t c0 = P0[a] >> 8, c1 = P1[a] >> 8;
     cell[a] = c0;
     sg[a] = d[a] > 0 ? 1 : (d[a] < 0 ? -1 : 0);
@@ -173,7 +179,7 @@ __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], 
     any |= left[a] != 0;
   }
   while (any) {
-    int64_t num[3], dn[3];
+    int32_t num[3], dn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       num[a] = sg[a] > 0 ? 256 * k[a] - P0[a] : P0[a] - 256 * k[a];
@@ -183,24 +189,26 @@ __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (left[a] == 0) continue;
-      if (best < 0 || num[a] * dn[best] < num[best] * dn[a]) best = a;
+      if (best < 0 || (int64_t)num[a] * dn[best] < (int64_t)num[best] * dn[a]) best = a;
     }
     bool grp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      grp[a] = left[a] != 0 && (a == best || num[a] * dn[best] == num[best] * dn[a]);
+      grp[a] = left[a] != 0 &&
+               (a == best || (int64_t)num[a] * dn[best] == (int64_t)num[best] * dn[a]);
     const int fa = grp[0] ? 0 : (grp[1] ? 1 : 2);
     int32_t ncell[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) ncell[a] = cell[a] + (grp[a] ? sg[a] : 0);
     Ev ev;
     ev.den = dn[fa];
-    const int64_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
+    const int32_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + nf * d[b];
+    for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + (int64_t)nf * d[b];
     const int exit_side = (fa == 0 ? sg[0] : (fa == 1 ? sg[1] : sg[2])) > 0 ? 1 : 0;
     ev.fa = fa;
     ev.exit_side = exit_side;
+    ev.planes = (int)grp[0] + (int)grp[1] + (int)grp[2];
 #pragma unroll
     for (int b = 0; b < 3; ++b) ev.ncell[b] = ncell[b];
     if (kCodes) {
@@ -239,12 +247,63 @@ __device__ inline Last shfl_last(const Last& v, int src) {
   return o;
 }
 
+// Plane crossings of segment P0 -> P1 and its last event, without walking
+// the events: the last event is the crossing of the largest parameter
+// (exact cross-multiplied comparison; on a tie the lowest axis, the face the
+// walk in for_each_event gives a simultaneous event), and it enters the
+// segment's final voxel.
+__device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
+                                      const GridArgs& ga, Last& out) {
+  int64_t d[3], num[3], dn[3];
+  int32_t c1[3];
+  uint32_t cross = 0;
+  bool has[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a] = (int64_t)P1[a] - P0[a];
+    const int32_t c0 = P0[a] >> 8;
+    c1[a] = P1[a] >> 8;
+    const uint32_t n = (uint32_t)abs(c1[a] - c0);
+    cross += n;
+    has[a] = n != 0;
+    num[a] = d[a] > 0 ? 256 * (int64_t)c1[a] - P0[a] : P0[a] - 256 * ((int64_t)c1[a] + 1);
+    dn[a] = d[a] > 0 ? d[a] : -d[a];
+  }
+  if (cross == 0) return 0;
+  int fa = -1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!has[a]) continue;
+    if (fa < 0) {
+      fa = a;
+    } else {
+      const int64_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
+      const int64_t df = fa == 0 ? dn[0] : (fa == 1 ? dn[1] : dn[2]);
+      if (num[a] * df > nf * dn[a]) fa = a;
+    }
+  }
+  const int64_t den = fa == 0 ? dn[0] : (fa == 1 ? dn[1] : dn[2]);
+  const int64_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
+  const int64_t df = fa == 0 ? d[0] : (fa == 1 ? d[1] : d[2]);
+  int64_t xn[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) xn[b] = (int64_t)P0[b] * den + nf * d[b];
+  out.has = 1;
+  out.xn0 = xn[0];
+  out.xn1 = xn[1];
+  out.xn2 = xn[2];
+  out.den = den;
+  out.entry = face_code(fa, df > 0 ? 0 : 1, xn, den, c1, ga);
+  return cross;
+}
+
 // Lines of every curve in curve order: the line inside a voxel runs from
 // one event's entry point to the next event's exit point; it is dropped if
-// the two exact points or the two quantized endpoints coincide. Line r of a
-// curve (between its events r and r + 1) goes to slot slot_off[c] + r;
-// unused slots are marked invalid. Each line takes its rank in its voxel
-// with one atomic on the histogram.
+// the two exact points or the two quantized endpoints coincide. The line
+// ending at an event goes to slot slot_off[c] + (plane crossings of the curve
+// before that event) - 1; slots no line takes keep the invalid mark written
+// before the launch. Each line takes its rank in its voxel with one atomic on
+// the histogram.
 template <bool kFloatIn>
 __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
@@ -270,26 +329,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
       load_vertex<kFloatIn>(xyz, lat, i, sa, P0);
       load_vertex<kFloatIn>(xyz, lat, i + 1, sa, P1);
     }
-    // pass 1: number of events and the last one (face codes only for the last)
+    // pass 1: plane crossings and the last event. Lines are numbered by
+    // crossings (an event of k simultaneous planes uses k numbers), so the
+    // numbering needs no walk; the unused numbers stay invalid slots.
     uint32_t e = 0;
     Last mine{0, 0, 0, 0, 1, 0u};
-    if (valid) {
-      Ev lastev{};
-      for_each_event<false>(P0, P1, ga, [&](const Ev& ev, const int32_t*) {
-        ++e;
-        lastev = ev;
-      });
-      if (e > 0) {
-        mine.has = 1;
-        mine.xn0 = lastev.xn[0];
-        mine.xn1 = lastev.xn[1];
-        mine.xn2 = lastev.xn[2];
-        mine.den = lastev.den;
-        mine.entry = face_code(lastev.fa, 1 - lastev.exit_side, lastev.xn, lastev.den,
-                               lastev.ncell, ga);
-      }
-    }
-    // exclusive prefix sum of the event counts
+    if (valid) e = last_event(P0, P1, ga, mine);
+    // exclusive prefix sum of the crossing counts
     uint32_t inc = e;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -321,9 +367,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
             const bool same = prev.xn0 * ev.den == ev.xn[0] * prev.den &&
                               prev.xn1 * ev.den == ev.xn[1] * prev.den &&
                               prev.xn2 * ev.den == ev.xn[2] * prev.den;
-            if (same || prev.entry == ev.exit_code) {
-              vox_out[w] = LS_INVALID_VOXEL;
-            } else {
+            if (!same && prev.entry != ev.exit_code) {
               const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
               rec_out[w] = (uint64_t)prev.entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
               vox_out[w] = vid;
@@ -337,7 +381,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
         prev.xn2 = ev.xn[2];
         prev.den = ev.den;
         prev.entry = ev.entry_code;
-        ++g;
+        g += (uint64_t)ev.planes;
       });
     }
     // carry the chunk's last event
@@ -345,8 +389,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     if (last_src >= 0) carry = shfl_last(mine, last_src);
     g0 += total;
   }
-  // slots past the curve's last line
-  for (uint64_t w = w0 + (g0 > 0 ? g0 - 1 : 0) + lane; w < w_end; w += 64) vox_out[w] = LS_INVALID_VOXEL;
+
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const uint32_t* rank,
@@ -641,6 +684,7 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
       (rc = rank.alloc(sizeof(uint32_t) * n_slots)) ||
       (rc = sums32.alloc(sizeof(uint32_t) * scan_block_sums_len(s->nvox))))
     return rc;
+  if ((rc = fill_u32(vox.as<uint32_t>(), LS_INVALID_VOXEL, (int64_t)n_slots, st))) return rc;
   if (C > 0) {
     if (float_in)
       hipLaunchKernelGGL((k_emit<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
