@@ -28,11 +28,14 @@ COPY_CAL_BYTES = 2 << 30
 
 # HBM bytes the ray caster moves per launch on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-#   python3 bench.py --steps 1 --warmup 0 --no-batch --no-cpu-baseline --copy-calibration
+#   python3 bench.py --steps 1 --warmup 0 --no-batch --no-serve --no-cpu-baseline --copy-calibration
 # each scaled by the counter's reading for the appended 2 GiB copy (true bytes /
 # counted bytes). The figure holds for the kernel source it was measured on
 # only: bench reports it when csrc/render.hip still has this sha256, else null.
-RENDER_TRAFFIC = None
+RENDER_TRAFFIC = {
+    "render_hip_sha256": "bb0eb207330d7de21bcddf8dde5343aee7b3c8b3eb49b60730b5b87caa4859a8",
+    "bytes_per_launch": 91808624,
+}
 
 
 def log(*a):
@@ -432,6 +435,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_GB_s": (traffic / (render_ms * 1e-3) / 1e9) if traffic else None,
             "algorithmic_bytes_per_launch": int(render_bytes),
             "avg_launch_ms": render_ms,
         },
