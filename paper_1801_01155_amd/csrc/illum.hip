@@ -79,15 +79,15 @@ __device__ inline float sample(const Pyramid& P, int lv, const int32_t v[3], con
     for (int k = 0; k < 4; ++k) {
       float2 pr;
       __builtin_memcpy(&pr, r + rows[k] + j, sizeof(pr));
-      c[k] = pr.x + wx * (pr.y - pr.x);
+      c[k] = __builtin_fmaf(wx, pr.y - pr.x, pr.x);
     }
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = r[rows[k]];
   }
-  const float c0 = c[0] * (1.f - fr[1]) + c[1] * fr[1];
-  const float c1 = c[2] * (1.f - fr[1]) + c[3] * fr[1];
-  return c0 * (1.f - fr[2]) + c1 * fr[2];
+  const float c0 = __builtin_fmaf(fr[1], c[1] - c[0], c[0]);
+  const float c1 = __builtin_fmaf(fr[1], c[3] - c[2], c[2]);
+  return __builtin_fmaf(fr[2], c1 - c0, c0);
 }
 
 // Occlusion along one cone from the centre of voxel v. A sample point
@@ -111,7 +111,7 @@ __device__ inline float cone(const Pyramid& P, const Sched& S, const int32_t v[3
       if (!inside) break;
     }
     const float f[3] = {0.5f + s * u32[0], 0.5f + s * u32[1], 0.5f + s * u32[2]};
-    occ += sample(P, S.lv[k], v, f) * S.D[k];
+    occ = __builtin_fmaf(sample(P, S.lv[k], v, f), S.D[k], occ);
     if (occ >= 1.f) break;
   }
   return occ < 1.f ? occ : 1.f;
@@ -179,7 +179,7 @@ struct TileLevels {
   int32_t tiles_per_xcd;
 };
 
-// Tap offset (in floats, within the sample's box) and weight of one axis.
+// Tap offset (in bytes, within the sample's box) and weight of one axis.
 struct Tap {
   int32_t off;
   float w;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
     const float fl = floorf(x);
     const int32_t li = min(max((p >> lv) + (int32_t)fl + TL.m[q], 0), sz - 2);
     const int32_t stride = a == 0 ? 1 : (a == 1 ? sz : sz * sz);
-    tab[e] = Tap{li * stride, x - fl};
+    tab[e] = Tap{li * stride * (int32_t)sizeof(float), x - fl};
   }
   __syncthreads();
   const float inv_n = 1.f / (float)C.n;
@@ -268,14 +268,16 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
           const Tap* tk = tc + 24 * k;
           const Tap ex = tk[pl[0]], ey = tk[8 + pl[1]], ez = tk[16 + pl[2]];
           const int sz = ksz[k], sz2 = sz * sz;
-          const float* bp = lds + kbase[k] + ex.off + ey.off + ez.off;
-          const float c00 = bp[0] + ex.w * (bp[1] - bp[0]);
-          const float c10 = bp[sz] + ex.w * (bp[sz + 1] - bp[sz]);
-          const float c01 = bp[sz2] + ex.w * (bp[sz2 + 1] - bp[sz2]);
-          const float c11 = bp[sz2 + sz] + ex.w * (bp[sz2 + sz + 1] - bp[sz2 + sz]);
-          const float c0 = c00 + ey.w * (c10 - c00);
-          const float c1 = c01 + ey.w * (c11 - c01);
-          occ += (c0 + ez.w * (c1 - c0)) * kD[k];
+          const float* bp = reinterpret_cast<const float*>(
+              reinterpret_cast<const char*>(lds + kbase[k]) + (ex.off + ey.off + ez.off));
+          // lerp(a, b, w) = a + w (b - a), fused
+          const float c00 = __builtin_fmaf(ex.w, bp[1] - bp[0], bp[0]);
+          const float c10 = __builtin_fmaf(ex.w, bp[sz + 1] - bp[sz], bp[sz]);
+          const float c01 = __builtin_fmaf(ex.w, bp[sz2 + 1] - bp[sz2], bp[sz2]);
+          const float c11 = __builtin_fmaf(ex.w, bp[sz2 + sz + 1] - bp[sz2 + sz], bp[sz2 + sz]);
+          const float c0 = __builtin_fmaf(ey.w, c10 - c00, c00);
+          const float c1 = __builtin_fmaf(ey.w, c11 - c01, c01);
+          occ = __builtin_fmaf(__builtin_fmaf(ez.w, c1 - c0, c0), kD[k], occ);
           go = occ < 1.f;
         }
       }

@@ -33,8 +33,8 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSortSlots = 4;
-constexpr int kStage = 4;       // records of a list loaded together
+constexpr int kSortSlots = 4;   // sorted hit buffer of the neighbour mode
+constexpr int kCoopSlots = 4;   // sorted hit buffer of the wave-cooperative own-list mode (8 measured slower)
 constexpr int kMergeSlots = 8;
 constexpr int kXcds = 8;
 
@@ -284,13 +284,13 @@ __device__ __attribute__((always_inline)) inline void composite(const RenderArgs
 }
 
 // Sorted register buffer of hits. Key (t, idx) lexicographic.
-template <typename TKey>
+template <typename TKey, int K = kSortSlots>
 struct HitBuf {
-  TKey t[kSortSlots];
-  float so[kSortSlots];
-  uint32_t idx[kSortSlots];
-  uint32_t aux[kSortSlots];
-  uint64_t rec[kSortSlots];
+  TKey t[K];
+  float so[K];
+  uint32_t idx[K];
+  uint32_t aux[K];
+  uint64_t rec[K];
   int n = 0;
   int dropped = 0;
 
@@ -299,14 +299,14 @@ struct HitBuf {
   }
 
   __device__ inline void insert(TKey tk, float sout, uint32_t id, uint32_t ax, uint64_t rc) {
-    if (n == kSortSlots && !less(tk, id, t[kSortSlots - 1], idx[kSortSlots - 1])) {
+    if (n == K && !less(tk, id, t[K - 1], idx[K - 1])) {
       ++dropped;
       return;
     }
-    if (n == kSortSlots) ++dropped;
+    if (n == K) ++dropped;
     // carry the new entry down the sorted array, swapping with larger keys
 #pragma unroll
-    for (int i = 0; i < kSortSlots; ++i) {
+    for (int i = 0; i < K; ++i) {
       bool occupied = i < n;
       bool sw = !occupied || less(tk, id, t[i], idx[i]);
       if (sw) {
@@ -327,13 +327,13 @@ struct HitBuf {
         if (!occupied) break;
       }
     }
-    if (n < kSortSlots) ++n;
+    if (n < K) ++n;
   }
 
   // Removes the smallest entry (slot 0), shifting the others down.
   __device__ inline void pop_front() {
 #pragma unroll
-    for (int i = 0; i + 1 < kSortSlots; ++i) {
+    for (int i = 0; i + 1 < K; ++i) {
       t[i] = t[i + 1];
       so[i] = so[i + 1];
       idx[i] = idx[i + 1];
@@ -509,104 +509,6 @@ __device__ inline void local_origin(const Ray& ray, double t, const int32_t cell
   for (int a = 0; a < 3; ++a) q[a] = (float)(fma(t, (double)ray.d[a], ray.od[a]) - (double)cell[a]);
 }
 
-// Own-list mode: test the voxel's lines, accept t >= 0, composite in
-// (t, index) order.
-__device__ __attribute__((always_inline)) inline void voxel_fast(const RenderArgs& R, const float4* lut_lds, const Ray& ray,
-                                  const int32_t vcell[3], double vt0, const Shade& S, float dd,
-                                  float inv_dd, uint32_t lo, uint32_t hi, Accum& acc,
-                                  Counts& cnt) {
-  float q[3];
-  local_origin(ray, vt0, vcell, q);
-  if (R.opaque) {
-    float best = INFINITY;
-    uint32_t bi = 0xFFFFFFFFu;
-    // records are loaded kStage at a time, all loads in flight together
-    for (uint32_t k0 = lo; k0 < hi; k0 += kStage) {
-      uint64_t st[kStage];
-#pragma unroll
-      for (int j = 0; j < kStage; ++j) st[j] = k0 + j < hi ? R.records[k0 + j] : 0ull;
-#pragma unroll
-      for (int j = 0; j < kStage; ++j) {
-        const uint32_t k = k0 + j;
-        if (k >= hi) break;
-        const uint64_t rec = st[j];
-        float a[3], b[3], si, so;
-        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-        cnt.tested++;
-        if (capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so) && vt0 + (double)si >= 0.0) {
-          cnt.hits++;
-          if (si < best || (si == best && k < bi)) {
-            best = si;
-            bi = k;
-          }
-        }
-      }
-    }
-    cnt.list_bytes += 8u * (hi - lo);
-    if (bi != 0xFFFFFFFFu) {
-      const uint64_t rec = R.records[bi];
-      float a[3], b[3], p[3];
-      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
-      composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
-      acc.done = true;
-    }
-    return;
-  }
-  float last_t = -INFINITY;
-  uint32_t last_i = 0;
-  bool first = true;
-  for (;;) {
-    HitBuf<float> buf;
-    for (uint32_t k0 = lo; k0 < hi; k0 += kStage) {
-      uint64_t st[kStage];
-#pragma unroll
-      for (int j = 0; j < kStage; ++j) st[j] = k0 + j < hi ? R.records[k0 + j] : 0ull;
-#pragma unroll
-      for (int j = 0; j < kStage; ++j) {
-        const uint32_t k = k0 + j;
-        if (k >= hi) break;
-        const uint64_t rec = st[j];
-        float a[3], b[3], si, so;
-        decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-        decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-        cnt.tested++;
-        if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
-        if (!(vt0 + (double)si >= 0.0)) continue;
-        if (!first && !HitBuf<float>::less(last_t, last_i, si, k)) continue;
-        if (first) cnt.hits++;
-        buf.insert(si, so, k, 0u, rec);
-      }
-    }
-    cnt.list_bytes += 8u * (hi - lo);
-    // the pass's last key bounds the next pass (read before consuming)
-    last_t = buf.t[kSortSlots - 1];
-    last_i = buf.idx[kSortSlots - 1];
-    const bool more = buf.dropped != 0;
-    while (buf.n > 0 && !acc.done) {
-      const float t_in = buf.t[0], t_out = buf.so[0];
-      const uint64_t rec = buf.rec[0];
-      buf.pop_front();
-      if (R.merge) {
-        const uint32_t tag = (uint32_t)(rec >> 40);
-        if (merge_hit(acc, tag, vt0 + (double)t_in, vt0 + (double)t_out, cnt)) continue;
-      }
-      float a[3], b[3], p[3];
-      decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
-      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
-      composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
-    }
-    if (acc.done || !more) break;
-    first = false;
-    cnt.passes++;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Wave-cooperative list tests (own-list mode). In one step of the grid walk
 // only some lanes stand in a non-empty voxel, and their lists differ in
@@ -722,7 +624,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
     }
     return;
   }
-  // transparent: passes of up to kSortSlots hits per owner, in (t, index) order
+  // transparent: passes of up to kCoopSlots hits per owner, in (t, index) order
   bool need = n != 0u;
   bool first = true;
   float last_t = -INFINITY;
@@ -731,7 +633,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
     const uint32_t np = need ? n : 0u;
     uint32_t N;
     const uint32_t P = wave_excl_scan(np, N);
-    HitBuf<float> buf;
+    HitBuf<float, kCoopSlots> buf;
     for (uint32_t base = 0; base < N; base += 64) {
       const uint32_t w = base + (uint32_t)lane;
       const int r = pair_owner(P, w);
@@ -756,7 +658,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         cnt.tested++;
         // t >= 0 and the pass filter are applied here, so only kept hits are pulled
         hit = capsule(qr, dr, ddr, iddr, a, b, R.r2, si, so) && vt0r + (double)si >= 0.0 &&
-              (firstr || HitBuf<float>::less(ltr, lir, si, k));
+              (firstr || HitBuf<float, kCoopSlots>::less(ltr, lir, si, k));
       }
       unsigned long long m =
           __ballot(hit) & bit_range(max((int)P - (int)base, 0), min((int)(P + np) - (int)base, 64));
@@ -774,8 +676,8 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
     if (need) {
       cnt.list_bytes += 8u * n;
       // the pass's last key bounds the next pass (read before consuming)
-      last_t = buf.t[kSortSlots - 1];
-      last_i = buf.idx[kSortSlots - 1];
+      last_t = buf.t[kCoopSlots - 1];
+      last_i = buf.idx[kCoopSlots - 1];
       const bool more = buf.dropped != 0;
       while (buf.n > 0 && !acc.done) {
         const float t_in = buf.t[0], t_out = buf.so[0];
