@@ -58,6 +58,7 @@ __device__ inline void decode_point(uint32_t code, float inv_bins, float p[3]) {
 }
 
 __device__ inline float dot3(const float a[3], const float b[3]) {
+  #pragma clang fp contract(fast)
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
@@ -68,6 +69,9 @@ __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline bool capsule(const float q[3], const float d[3], float dd, float inv_dd,
                                const float a[3], const float b[3], float r2, float& t_in,
                                float& t_out) {
+  // fp32 shading and intersection arithmetic may fuse multiply-adds (the
+  // grid walk and ray set-up use explicitly rounded fp64 operations)
+  #pragma clang fp contract(fast)
   float lo = INFINITY, hi = -INFINITY;
   float oa[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
   float ob[3] = {q[0] - b[0], q[1] - b[1], q[2] - b[2]};
@@ -133,6 +137,7 @@ __device__ inline bool capsule(const float q[3], const float d[3], float dd, flo
 // point cell + p (p local).
 __device__ inline float grid_lookup(const float* grid, const int32_t g[3], const int32_t cell[3],
                                     const float p[3]) {
+  #pragma clang fp contract(fast)
   int32_t i0[3], i1[3];
   float f[3];
 #pragma unroll
@@ -240,6 +245,7 @@ struct Shade {
 __device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const float4* lut_lds, const Shade& S, Accum& acc, uint64_t rec,
                                  const int32_t cell[3], const float p[3], const float a[3],
                                  const float b[3], Counts& cnt) {
+  #pragma clang fp contract(fast)
   const int attr = (int)((rec >> 32) & 0xFF);
   const float4 lut = lut_lds[attr];
   const float alpha = R.opaque ? 1.f : lut.w;
