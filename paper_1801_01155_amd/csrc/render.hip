@@ -921,18 +921,52 @@ __device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
 
 template <int kMode, bool kCount>
 __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
-  // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
-  // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every XCD
-  // gets a share of the part of the screen the grid covers.
   const int b = blockIdx.x;
-  const int x = b % kXcds, l = b / kXcds;
-  const int row = x + kXcds * (l / R.tiles_x);
-  const int tile = row * R.tiles_x + l % R.tiles_x;
+  int tile;
+  bool live;
+  if (R.spiral_r >= 0) {
+    // Tiles in square rings around the projection of the grid centre, where
+    // rays cross the most voxels: the costliest tiles start first instead of
+    // setting the frame's tail. Ring r holds workgroups [(2r-1)^2, (2r+1)^2).
+    int s = (int)sqrtf((float)b);
+    while (s * s > b) --s;
+    while ((s + 1) * (s + 1) <= b) ++s;
+    const int r = (s + 1) / 2;
+    int dx = 0, dy = 0;
+    if (r > 0) {
+      const int k = b - (2 * r - 1) * (2 * r - 1), side = 2 * r;
+      if (k < side) {
+        dx = r;
+        dy = -r + 1 + k;
+      } else if (k < 2 * side) {
+        dx = r - 1 - (k - side);
+        dy = r;
+      } else if (k < 3 * side) {
+        dx = -r;
+        dy = r - 1 - (k - 2 * side);
+      } else {
+        dx = -r + 1 + (k - 3 * side);
+        dy = -r;
+      }
+    }
+    const int tx = R.spiral_x + dx, ty = R.spiral_y + dy;
+    const int tiles_y = R.n_tiles / R.tiles_x;
+    live = tx >= 0 && ty >= 0 && tx < R.tiles_x && ty < tiles_y;
+    tile = ty * R.tiles_x + tx;
+  } else {
+    // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
+    // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every
+    // XCD gets a share of the part of the screen the grid covers.
+    const int x = b % kXcds, l = b / kXcds;
+    const int row = x + kXcds * (l / R.tiles_x);
+    tile = row * R.tiles_x + l % R.tiles_x;
+    live = row * R.tiles_x < R.n_tiles;
+  }
   __shared__ float4 lut_lds[256];
   extern __shared__ double dyn_lds[];
   const MergeLds merge_lds = merge_lds_view(dyn_lds);
   Counts cnt;
-  if (row * R.tiles_x >= R.n_tiles) {
+  if (!live) {
     if (kCount) flush_counts(R.counters, cnt);
     return;
   }
@@ -1054,13 +1088,51 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   const int tiles_y = (R.H + 8 * wy - 1) / (8 * wy);
   R.n_tiles = R.tiles_x * tiles_y;
   R.tiles_per_xcd = (R.n_tiles + kXcds - 1) / kXcds;
+  R.spiral_r = -1;
+  {
+    // screen position of the grid centre (camera vectors taken as orthogonal;
+    // this only orders the launch)
+    double p[3], F2 = 0, R2 = 0, U2 = 0, pF = 0, pR = 0, pU = 0;
+    for (int a = 0; a < 3; ++a) {
+      p[a] = 0.5 * s->grid[a] - cam->eye[a];
+      F2 += (double)cam->forward[a] * cam->forward[a];
+      R2 += (double)cam->right[a] * cam->right[a];
+      U2 += (double)cam->up[a] * cam->up[a];
+      pF += p[a] * cam->forward[a];
+      pR += p[a] * cam->right[a];
+      pU += p[a] * cam->up[a];
+    }
+    double u = 0, v = 0;
+    bool ok = R2 > 0 && U2 > 0;
+    if (ok && !cam->orthographic) {
+      ok = F2 > 0 && pF > 0;
+      const double sc = ok ? pF / F2 : 1.0;
+      u = pR / (sc * R2);
+      v = pU / (sc * U2);
+    } else if (ok) {
+      u = pR / R2;
+      v = pU / U2;
+    }
+    if (ok && std::isfinite(u) && std::isfinite(v)) {
+      const double fi = (u + 1.0) * 0.5 * R.W, fj = (1.0 - v) * 0.5 * R.H;
+      const int ty_n = R.n_tiles / R.tiles_x;
+      int cx = (int)std::floor(fi / (8.0 * wx)), cy = (int)std::floor(fj / (8.0 * wy));
+      cx = std::min(std::max(cx, 0), R.tiles_x - 1);
+      cy = std::min(std::max(cy, 0), ty_n - 1);
+      R.spiral_x = cx;
+      R.spiral_y = cy;
+      R.spiral_r = std::max(std::max(cx, R.tiles_x - 1 - cx), std::max(cy, ty_n - 1 - cy));
+    }
+  }
   *Rp = R;
   return LS_OK;
 }
 
 int launch_render(const RenderArgs& R, hipStream_t st) {
   const int tiles_y = R.n_tiles / R.tiles_x;
-  const unsigned blocks = (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
+  const unsigned blocks =
+      R.spiral_r >= 0 ? (unsigned)((2 * R.spiral_r + 1) * (2 * R.spiral_r + 1))
+                      : (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
   const unsigned threads = (unsigned)(64 * R.wx * R.wy);
   const size_t lds = merge_lds_bytes(threads);
   if (R.mode == 0) {

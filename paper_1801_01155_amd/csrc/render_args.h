@@ -25,6 +25,10 @@ struct RenderArgs {
   RenderCounters* counters;
   int32_t wx, wy;                 // tile = wx x wy waves of 8 x 8 pixels
   int32_t tiles_x, n_tiles, tiles_per_xcd;
+  // plain launch order: tiles in square rings around the tile (spiral_x,
+  // spiral_y) out to ring spiral_r, or rows interleaved over the XCDs when
+  // spiral_r < 0
+  int32_t spiral_x, spiral_y, spiral_r;
 };
 
 // Tile queues of the persistent kernel: one contiguous range per XCD.
