@@ -84,7 +84,7 @@ int ls_alloc(ls_lineset* s, void** p, size_t bytes) {
 
 void ls_free_all(ls_lineset* s) {
   void* ptrs[] = {s->offsets, s->records, s->occupancy, s->lod_count, s->lod_len,
-                  s->lod_rho, s->ao,      s->sh};
+                  s->lod_rho, s->ao,      s->sh,        s->cone_tab};
   bool any = false;
   for (void* p : ptrs) any = any || p;
   // work queued on any stream may still read the set (hipFree would wait too)
@@ -94,6 +94,8 @@ void ls_free_all(ls_lineset* s) {
   s->records = nullptr;
   s->occupancy = nullptr;
   s->lod_count = s->lod_len = s->lod_rho = s->ao = s->sh = nullptr;
+  s->cone_tab = nullptr;
+  s->cone_tab_bytes = 0;
   s->bytes = 0;
 }
 

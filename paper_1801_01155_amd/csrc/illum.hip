@@ -166,6 +166,7 @@ constexpr int kTileThreads = 256;
 constexpr int kTileSlots = 4;            // levels 0..3
 constexpr int kTileLdsBytes = 49152;
 constexpr int kTileMaxSamples = 8;       // instantiated schedule lengths
+constexpr size_t kMaxTabBytes = 8u * kMaxCones * kTileMaxSamples * 24;   // Tap tables
 
 struct TileLevels {
   int32_t n;                        // distinct levels of the schedule
@@ -187,9 +188,31 @@ struct Tap {
 
 // kN = S.n: the sample loop is unrolled, so the schedule's per-sample
 // constants (box, edge, weight) stay in scalar registers for the whole block.
+// Tap table entry ((c * S.n + k) * 3 + a) * 8 + p: the box offset and
+// weight of cone c, sample k, axis a for a voxel at position p of the tile.
+template <int kN>
+__global__ __launch_bounds__(kTileThreads) void k_cone_table(Cones C, Sched S, TileLevels TL,
+                                                             Tap* tab) {
+  const int n_tab = C.n * kN * 24;
+  for (int e = threadIdx.x; e < n_tab; e += kTileThreads) {
+    const int p = e & 7, a = (e >> 3) % 3, ck = e / 24;
+    const int c = ck / kN, k = ck % kN;
+    const int q = TL.slot[k], lv = S.lv[k], sz = TL.sz[q];
+    const float u = (float)C.dir[c][a];
+    const float f = 0.5f + S.s[k] * u;
+    const float x = ((float)(p & ((1 << lv) - 1)) + f) * __builtin_ldexpf(1.0f, -lv) - 0.5f;
+    const float fl = floorf(x);
+    const int32_t li = min(max((p >> lv) + (int32_t)fl + TL.m[q], 0), sz - 2);
+    const int32_t stride = a == 0 ? 1 : (a == 1 ? sz : sz * sz);
+    tab[e] = Tap{li * stride * (int32_t)sizeof(float), x - fl};
+  }
+}
+
 template <int kN>
 __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C, Sched S,
-                                                              TileLevels TL, float* out) {
+                                                              TileLevels TL,
+                                                              const Tap* __restrict__ tab_g,
+                                                              float* out) {
   extern __shared__ float lds[];
   // XCD x (= block mod 8) works through a contiguous run of tiles, so the
   // boxes neighbouring tiles share are fetched into one L2.
@@ -214,20 +237,13 @@ __global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C
       box[i] = r[(z * dy + y) * dx + x];
     }
   }
-  // tap tables: entry ((c * S.n + k) * 3 + a) * 8 + p
+  // tap tables (built once per launch by k_cone_table) into LDS
   Tap* tab = reinterpret_cast<Tap*>(lds + TL.table);
-  const int n_tab = C.n * kN * 24;
-  for (int e = threadIdx.x; e < n_tab; e += kTileThreads) {
-    const int p = e & 7, a = (e >> 3) % 3, ck = e / 24;
-    const int c = ck / kN, k = ck % kN;
-    const int q = TL.slot[k], lv = S.lv[k], sz = TL.sz[q];
-    const float u = (float)C.dir[c][a];
-    const float f = 0.5f + S.s[k] * u;
-    const float x = ((float)(p & ((1 << lv) - 1)) + f) * __builtin_ldexpf(1.0f, -lv) - 0.5f;
-    const float fl = floorf(x);
-    const int32_t li = min(max((p >> lv) + (int32_t)fl + TL.m[q], 0), sz - 2);
-    const int32_t stride = a == 0 ? 1 : (a == 1 ? sz : sz * sz);
-    tab[e] = Tap{li * stride * (int32_t)sizeof(float), x - fl};
+  {
+    const int n4 = C.n * kN * 24 / 2;   // two Taps per 16-byte word
+    const int4* src = reinterpret_cast<const int4*>(tab_g);
+    int4* dst = reinterpret_cast<int4*>(tab);
+    for (int e = threadIdx.x; e < n4; e += kTileThreads) dst[e] = src[e];
   }
   __syncthreads();
   const float inv_n = 1.f / (float)C.n;
@@ -356,7 +372,7 @@ bool make_tile_levels(const ls_lineset* s, const Sched& S, int n_cones, TileLeve
     total += (int64_t)T->sz[q] * T->sz[q] * T->sz[q];
   }
   T->base[T->n] = (int32_t)total;
-  total += total & 1;                          // 8-byte alignment of the tables
+  total = (total + 3) & ~(int64_t)3;           // 16-byte alignment of the tables
   T->table = (int32_t)total;
   total += (int64_t)n_cones * S.n * 24 * 2;    // Tap = 2 floats
   if (total * 4 > kTileLdsBytes) return false;
@@ -371,7 +387,7 @@ size_t tile_lds_bytes(const TileLevels& T, int n_cones, int n_samples) {
   return sizeof(float) * ((size_t)T.table + (size_t)n_cones * n_samples * 24 * 2);
 }
 
-int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
+int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
                  bool ao) {
   // the tiled kernel pays one LDS fill per tile; with few samples per voxel
   // (the single shadow cone) direct gathers are cheaper
@@ -380,9 +396,20 @@ int launch_cones(const ls_lineset* s, const Cones& C, const Sched& S, float* out
     const size_t lds = tile_lds_bytes(T, C.n, S.n);
     const dim3 grid((unsigned)(8 * T.tiles_per_xcd)), block(kTileThreads);
     const Pyramid P = make_pyramid(s);
+    // the tap tables: one small launch, then copied by every block
+    const size_t tab_bytes = sizeof(Tap) * (size_t)C.n * S.n * 24;
+    int rc;
+    if (!s->cone_tab || s->cone_tab_bytes < tab_bytes) {
+      if ((rc = ls_alloc(s, &s->cone_tab, kMaxTabBytes))) return rc;
+      s->cone_tab_bytes = kMaxTabBytes;
+    }
+    Tap* tab = static_cast<Tap*>(s->cone_tab);
     switch (S.n) {
-#define LS_CONES_CASE(N) \
-  case N: hipLaunchKernelGGL(k_cones_tiled<N>, grid, block, lds, st, P, C, S, T, out); break;
+#define LS_CONES_CASE(N)                                                                        \
+  case N:                                                                                       \
+    hipLaunchKernelGGL(k_cone_table<N>, dim3(1), block, 0, st, C, S, T, tab);                   \
+    hipLaunchKernelGGL(k_cones_tiled<N>, grid, block, lds, st, P, C, S, T, tab, out);          \
+    break;
       LS_CONES_CASE(1) LS_CONES_CASE(2) LS_CONES_CASE(3) LS_CONES_CASE(4)
       LS_CONES_CASE(5) LS_CONES_CASE(6) LS_CONES_CASE(7) LS_CONES_CASE(8)
 #undef LS_CONES_CASE

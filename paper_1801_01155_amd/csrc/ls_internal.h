@@ -47,6 +47,8 @@ struct ls_lineset {
   float* lod_rho;
   float* ao;
   float* sh;
+  void* cone_tab;         // tap tables of the tiled cone tracer
+  size_t cone_tab_bytes;
   double lo_scale[4];
   size_t bytes;
   int device;
