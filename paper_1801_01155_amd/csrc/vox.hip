@@ -442,61 +442,57 @@ __global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint
   records[lo + r] = rec[e];
 }
 
-// Non-empty voxel count and longest list: grid-stride loop, wave and block
-// reduction, one atomic per workgroup.
-__global__ __launch_bounds__(kBlock) void k_list_stats(const uint32_t* offsets, int64_t nvox,
-                                                       unsigned long long* nonempty,
-                                                       unsigned int* max_list) {
+// Occupancy mask per 4^3 macro cell: bit (x & 3) + 4 (y & 3) + 16 (z & 3) of
+// the cell's 64-bit word is set when that voxel's list is not empty. One
+// load tells the ray caster which voxels of the macro cell it can skip
+// (a zero word: the whole macro cell). The same pass counts the non-empty
+// voxels and the longest list (wave and block reduction, one atomic each per
+// workgroup).
+__global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, GridArgs ga,
+                                                      int32_t mx, int32_t my, int32_t mz,
+                                                      unsigned long long* occ,
+                                                      unsigned long long* nonempty,
+                                                      unsigned int* max_list) {
   __shared__ unsigned long long s_ne[kBlock / 64];
   __shared__ unsigned s_mx[kBlock / 64];
+  int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t nm = (int64_t)mx * my * mz;
   unsigned long long ne = 0;
-  unsigned mx = 0;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nvox;
-       v += (int64_t)gridDim.x * kBlock) {
-    const unsigned n = offsets[v + 1] - offsets[v];
-    ne += n > 0;
-    mx = n > mx ? n : mx;
+  unsigned mxl = 0;
+  if (m < nm) {
+    int32_t bx = (int32_t)(m % mx), by = (int32_t)((m / mx) % my),
+            bz = (int32_t)(m / ((int64_t)mx * my));
+    unsigned long long bits = 0;
+    for (int k = 0; k < 64; ++k) {
+      const int32_t x = 4 * bx + (k & 3), y = 4 * by + ((k >> 2) & 3), z = 4 * bz + (k >> 4);
+      if (x >= ga.g[0] || y >= ga.g[1] || z >= ga.g[2]) continue;
+      const int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
+      const unsigned n = offsets[v + 1] - offsets[v];
+      if (n > 0) bits |= 1ull << k;
+      mxl = n > mxl ? n : mxl;
+    }
+    occ[m] = bits;
+    ne = (unsigned long long)__popcll(bits);
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     ne += __shfl_xor(ne, d, 64);
-    const unsigned o = __shfl_xor(mx, d, 64);
-    mx = o > mx ? o : mx;
+    const unsigned o = __shfl_xor(mxl, d, 64);
+    mxl = o > mxl ? o : mxl;
   }
   if ((threadIdx.x & 63) == 0) {
     s_ne[threadIdx.x >> 6] = ne;
-    s_mx[threadIdx.x >> 6] = mx;
+    s_mx[threadIdx.x >> 6] = mxl;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / 64; ++w) {
       ne += s_ne[w];
-      mx = s_mx[w] > mx ? s_mx[w] : mx;
+      mxl = s_mx[w] > mxl ? s_mx[w] : mxl;
     }
     if (ne) atomicAdd(nonempty, ne);
-    if (mx) atomicMax(max_list, mx);
+    if (mxl) atomicMax(max_list, mxl);
   }
-}
-
-// Occupancy mask per 4^3 macro cell: bit (x & 3) + 4 (y & 3) + 16 (z & 3) of
-// the cell's 64-bit word is set when that voxel's list is not empty. One
-// load tells the ray caster which voxels of the macro cell it can skip
-// (a zero word: the whole macro cell).
-__global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, GridArgs ga,
-                                                      int32_t mx, int32_t my, int32_t mz,
-                                                      unsigned long long* occ) {
-  int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t nm = (int64_t)mx * my * mz;
-  if (m >= nm) return;
-  int32_t bx = (int32_t)(m % mx), by = (int32_t)((m / mx) % my), bz = (int32_t)(m / ((int64_t)mx * my));
-  unsigned long long bits = 0;
-  for (int k = 0; k < 64; ++k) {
-    const int32_t x = 4 * bx + (k & 3), y = 4 * by + ((k >> 2) & 3), z = 4 * bz + (k >> 4);
-    if (x >= ga.g[0] || y >= ga.g[1] || z >= ga.g[2]) continue;
-    const int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
-    if (offsets[v + 1] > offsets[v]) bits |= 1ull << k;
-  }
-  occ[m] = bits;
 }
 
 
@@ -722,20 +718,16 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
     LS_HIP(hipGetLastError());
   }
 
-  // 6. list statistics and macro-cell occupancy
+  // 6. macro-cell occupancy and list statistics
   DeviceBuf stats(st);
   if ((rc = stats.alloc(16))) return rc;
   LS_HIP(hipMemsetAsync(stats.p, 0, 16, st));
-  const unsigned stat_blocks = std::min<unsigned>(blocks_for(s->nvox), 2048u);
-  hipLaunchKernelGGL(k_list_stats, dim3(stat_blocks), dim3(kBlock), 0, st, s->offsets,
-                     s->nvox, stats.as<unsigned long long>(),
-                     (unsigned int*)(stats.as<char>() + 8));
-  LS_HIP(hipGetLastError());
   for (int a = 0; a < 3; ++a) s->macro[a] = (s->grid[a] + 3) / 4;
   int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
   if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * nm))) return rc;
   hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nm)), dim3(kBlock), 0, st, s->offsets, ga,
-                     s->macro[0], s->macro[1], s->macro[2], (unsigned long long*)s->occupancy);
+                     s->macro[0], s->macro[1], s->macro[2], (unsigned long long*)s->occupancy,
+                     stats.as<unsigned long long>(), (unsigned int*)(stats.as<char>() + 8));
   LS_HIP(hipGetLastError());
   unsigned long long hstats[2] = {0, 0};
   LS_HIP(hipMemcpyAsync(hstats, stats.p, 16, hipMemcpyDeviceToHost, st));
