@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "ls_internal.h"
@@ -64,6 +65,47 @@ struct Owned {
     for (void* p : v) pool_free(p);
   }
 };
+
+}  // namespace
+
+namespace {
+
+// One side stream (default priority, non-blocking) and a fork/join event pair
+// per device, created on first use and kept for the process; the mutex keeps
+// one caller's fork, side work and join together.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex mu;
+};
+
+std::mutex g_side_mu;
+SideStream g_side[64];
+
+SideStream* side_stream(int device) {
+  if (device < 0 || device >= 64) {
+    ls_set_error("device index %d out of range", device);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SideStream& S = g_side[device];
+  if (!S.stream) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    const bool ok = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) == hipSuccess &&
+                    hipEventCreateWithFlags(&S.join, hipEventDisableTiming) == hipSuccess;
+    if (cur != device) (void)hipSetDevice(cur);
+    if (!ok) {
+      (void)hipGetLastError();
+      ls_set_error("side stream creation failed");
+      S.stream = nullptr;
+      return nullptr;
+    }
+  }
+  return &S;
+}
 
 }  // namespace
 
@@ -307,6 +349,20 @@ int lineset_build_lod(ls_lineset_t s, const ls_lod_desc* d, void* hip_stream) {
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int rc;
   if ((rc = lod_build(s, d->lut_rgba, d->opaque, st))) return rc;
+  if (d->build_ao && d->build_shadow) {
+    // The shadow cone (latency-bound gathers) runs on a second stream beside
+    // the AO cones (VALU-bound), both after the pyramid, joined before return.
+    SideStream* side = side_stream(s->device);
+    if (!side) return LS_EDEVICE;
+    std::lock_guard<std::mutex> lk(side->mu);
+    LS_HIP(hipEventRecord(side->fork, st));
+    LS_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+    rc = illum_shadow(s, d->light_dir, d->cone_aperture, side->stream);
+    LS_HIP(hipEventRecord(side->join, side->stream));
+    if (!rc) rc = illum_ao(s, d->ao_cones, d->ao_radius, d->cone_aperture, st);
+    LS_HIP(hipStreamWaitEvent(st, side->join, 0));
+    return rc;
+  }
   if (d->build_ao && (rc = illum_ao(s, d->ao_cones, d->ao_radius, d->cone_aperture, st))) return rc;
   if (d->build_shadow && (rc = illum_shadow(s, d->light_dir, d->cone_aperture, st))) return rc;
   return LS_OK;
