@@ -146,161 +146,273 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, Sched S, 
   sh[v] = 1.f - cone(P, S, p, C.dir[0], near_any_face(P, p, S.reach));
 }
 
-// LDS-tiled cone tracing. A block handles an 8^3 tile of voxels. Every
-// sample k of every cone lies within s_k (voxel units) of its voxel, so on
-// level l the taps of the whole tile fall inside a box of
-// (tile extent on l) + 2 m_l cells per axis, m_l = ceil(max s_k / 2^l) + 2
-// over the samples on l. The block first copies each level's box into LDS
-// (coordinates clamped to the level, which makes plain trilinear
-// interpolation of the copy the clamp-to-edge interpolation of the level).
+// LDS-tiled cone tracing by voxel columns. A block handles a tile of
+// 16 x 16 x 8 voxels; each of its 256 threads owns one (x, y) column of the
+// tile and walks its 8 voxels along z. Every sample k of every cone lies
+// within s_k (voxel units) of its voxel, so on level l the taps of the whole
+// tile fall inside a box of (tile extent on l) + 2 m_l cells per axis,
+// m_l = ceil(max s_k / 2^l) + 2 over the samples on l. The block first
+// copies each level's box into LDS (coordinates clamped to the level, which
+// makes plain trilinear interpolation of the copy the clamp-to-edge
+// interpolation of the level).
 //
 // With the tile origin a multiple of 8 and every level at most 3, a sample's
 // lattice coordinate on axis a depends only on the cone, the sample and the
 // voxel's position p_a = v_a - t0_a in the tile: x = ((p_a mod 2^l) + 0.5 +
-// s u_a) 2^-l - 0.5 (the arithmetic of sample()). The block tabulates, per
-// (cone, sample, axis, p_a), the tap's offset in the box and the weight
-// frac(x); a sample then costs three table reads, eight tap reads and the
-// seven interpolations.
-constexpr int kTile = 8;
-constexpr int kTileThreads = 256;
-constexpr int kTileSlots = 4;            // levels 0..3
-constexpr int kTileLdsBytes = 49152;
-constexpr int kTileMaxSamples = 8;       // instantiated schedule lengths
-constexpr size_t kMaxTabBytes = 8u * kMaxCones * kTileMaxSamples * 24;   // Tap tables
+// s u_a) 2^-l - 0.5 (the arithmetic of sample()), cell floor(x) + (p_a >> l)
+// and weight frac(x). Along z, the voxels of one phase ph = p_z mod 2^l take
+// consecutive cells c_ph + (p_z >> l), and c_ph is c_0 or c_0 + 1. So for
+// one cone and sample a thread interpolates the (x, y) bilinear value of the
+// few z-planes c_0 .. c_0 + (8 >> l) + 1 once, and each voxel of the column
+// takes its z interpolation from two of them: the 8 voxels of a column share
+// 9 planes on level 0 and 3 on level 3, where per-voxel trilinear samples
+// would read 8 taps each. The x and y taps (per thread) come from a small
+// table in global memory, the z taps, plane choices and inside-the-grid
+// ranges of each (cone, sample) are wave-uniform (scalar loads). The order of
+// the interpolations (x, then y, then z) is that of sample().
+//
+// The inside-the-grid test of sample k (the fp64 expression of the
+// definition) holds on an interval of each voxel coordinate; the table
+// kernel finds the intervals by bisection, so the kernel compares integers.
+// A sample outside the grid adds nothing, and since the test is monotone
+// along the cone every later sample is outside too, which is where the
+// definition stops. Occlusion terms are non-negative, so accumulating past
+// saturation and clamping at the end gives the definition's value.
+constexpr int kColX = 16, kColY = 16, kColZ = 8;
+constexpr int kColThreads = kColX * kColY;
+constexpr int kColSlots = 4;             // levels 0..3
+constexpr int kColLdsBytes = 65536;
+constexpr int kColMaxSamples = 8;        // instantiated schedule lengths
 
-struct TileLevels {
+struct ColLevels {
   int32_t n;                        // distinct levels of the schedule
-  int32_t lv[kTileSlots];
-  int32_t m[kTileSlots];            // margin per side, cells
-  int32_t sz[kTileSlots];           // box edge, cells
-  int32_t base[kTileSlots + 1];     // LDS offset (floats) of each box; base[n] = total
+  int32_t lv[kColSlots];
+  int32_t m[kColSlots];             // margin per side, cells
+  int32_t sz[kColSlots][3];         // box extent per axis, cells
+  int32_t base[kColSlots + 1];      // LDS offset (floats) of each box; base[n] = total
   int32_t slot[kMaxSamples];        // box of each sample
-  int32_t table;                    // LDS offset (floats, even) of the tap tables
   int32_t tiles[3];
   int32_t tiles_per_xcd;
 };
 
-// Tap offset (in bytes, within the sample's box) and weight of one axis.
+// Tap offset (bytes, within the sample's box) and weight of one axis.
 struct Tap {
   int32_t off;
   float w;
 };
 
-// kN = S.n: the sample loop is unrolled, so the schedule's per-sample
-// constants (box, edge, weight) stay in scalar registers for the whole block.
-// Tap table entry ((c * S.n + k) * 3 + a) * 8 + p: the box offset and
-// weight of cone c, sample k, axis a for a voxel at position p of the tile.
-template <int kN>
-__global__ __launch_bounds__(kTileThreads) void k_cone_table(Cones C, Sched S, TileLevels TL,
-                                                             Tap* tab) {
-  const int n_tab = C.n * kN * 24;
-  for (int e = threadIdx.x; e < n_tab; e += kTileThreads) {
-    const int p = e & 7, a = (e >> 3) % 3, ck = e / 24;
-    const int c = ck / kN, k = ck % kN;
-    const int q = TL.slot[k], lv = S.lv[k], sz = TL.sz[q];
-    const float u = (float)C.dir[c][a];
-    const float f = 0.5f + S.s[k] * u;
-    const float x = ((float)(p & ((1 << lv) - 1)) + f) * __builtin_ldexpf(1.0f, -lv) - 0.5f;
-    const float fl = floorf(x);
-    const int32_t li = min(max((p >> lv) + (int32_t)fl + TL.m[q], 0), sz - 2);
-    const int32_t stride = a == 0 ? 1 : (a == 1 ? sz : sz * sz);
-    tab[e] = Tap{li * stride * (int32_t)sizeof(float), x - fl};
+// Per (cone, sample): the z planes and the inside-the-grid ranges.
+struct alignas(64) ZRec {
+  int32_t c0;          // byte offset in LDS of plane c_0 (box base included)
+  int32_t delta;       // bit ph: c_ph - c_0 (0 or 1)
+  int32_t lo[3], hi[3];  // inside-the-grid voxel ranges (lo > hi: none)
+  float w[8];          // z weight of phase ph
+};
+static_assert(sizeof(ZRec) == 64, "ZRec is one 64-byte scalar load");
+
+// Planes a column interpolates on level L for 8 voxels: (8 >> L) + 1 on
+// level 0 (one phase), one more on coarser levels (the phases' c_ph may
+// exceed c_0 by one).
+template <int L>
+constexpr int col_planes() {
+  return L == 0 ? 9 : (kColZ >> L) + 2;
+}
+
+__host__ __device__ inline int col_planes_rt(int L) { return L == 0 ? 9 : (kColZ >> L) + 2; }
+
+// Table layout (global memory): ZRec[n_cones * kN], then
+// Tap[n_cones * kN][2][16] (x taps by p_x, y taps by p_y).
+inline size_t col_table_bytes(int n_cones, int n_samples) {
+  return (size_t)n_cones * n_samples * (sizeof(ZRec) + 2 * 16 * sizeof(Tap));
+}
+constexpr size_t kMaxTabBytes = (size_t)kMaxCones * kColMaxSamples * (sizeof(ZRec) + 2 * 16 * sizeof(Tap));
+
+// Smallest v in [0, g) whose sample coordinate (v + 0.5) + s u is >= 0, and
+// the largest whose coordinate is < g (the coordinate grows with v).
+__device__ inline void inside_range(double s, double u, int32_t g, int32_t* lo, int32_t* hi) {
+  int32_t a = 0, b = g;                  // first v with x >= 0 lies in [a, b]
+  while (a < b) {
+    const int32_t mid = (a + b) >> 1;
+    if (((double)mid + 0.5) + s * u >= 0.0) b = mid; else a = mid + 1;
   }
+  *lo = a;
+  a = -1;
+  b = g - 1;                             // last v with x < g lies in [a, b]
+  while (a < b) {
+    const int32_t mid = (a + b + 1) >> 1;
+    if (((double)mid + 0.5) + s * u < (double)g) a = mid; else b = mid - 1;
+  }
+  *hi = a;
+}
+
+// Lattice cell (before the tile offset) and weight of axis coordinate p on
+// level lv for local offset f; the arithmetic of sample().
+__device__ inline void col_coord(int32_t p, int lv, float f, float* fl, float* w) {
+  const float x = ((float)(p & ((1 << lv) - 1)) + f) * __builtin_ldexpf(1.0f, -lv) - 0.5f;
+  *fl = floorf(x);
+  *w = x - *fl;
 }
 
 template <int kN>
-__global__ __launch_bounds__(kTileThreads) void k_cones_tiled(Pyramid P, Cones C, Sched S,
-                                                              TileLevels TL,
-                                                              const Tap* __restrict__ tab_g,
-                                                              float* out) {
+__global__ __launch_bounds__(kColThreads) void k_col_table(Pyramid P, Cones C, Sched S,
+                                                           ColLevels CL, ZRec* zt, Tap* xyt) {
+  const int n_ck = C.n * kN;
+  for (int e = threadIdx.x; e < n_ck * 32; e += kColThreads) {
+    const int p = e & 15, a = (e >> 4) & 1, ck = e >> 5;
+    const int c = ck / kN, k = ck % kN;
+    const int q = CL.slot[k], lv = S.lv[k];
+    const float f = 0.5f + S.s[k] * (float)C.dir[c][a];
+    float fl, w;
+    col_coord(p, lv, f, &fl, &w);
+    const int32_t li = min(max((p >> lv) + (int32_t)fl + CL.m[q], 0), CL.sz[q][a] - 2);
+    const int32_t stride = a == 0 ? 1 : CL.sz[q][0];
+    xyt[e] = Tap{li * stride * (int32_t)sizeof(float), w};
+  }
+  for (int ck = threadIdx.x; ck < n_ck; ck += kColThreads) {
+    const int c = ck / kN, k = ck % kN;
+    const int q = CL.slot[k], lv = S.lv[k];
+    const float f = 0.5f + S.s[k] * (float)C.dir[c][2];
+    ZRec r{};
+    float fl0, w;
+    col_coord(0, lv, f, &fl0, &w);
+    const int nph = 1 << lv;
+    for (int ph = 0; ph < 8; ++ph) {
+      float fl;
+      col_coord(ph, lv, f, &fl, &w);
+      r.w[ph] = ph < nph ? w : 0.f;
+      if (ph < nph && fl > fl0) r.delta |= 1 << ph;
+    }
+    const int32_t c0 = min(max((int32_t)fl0 + CL.m[q], 0), CL.sz[q][2] - col_planes_rt(lv));
+    r.c0 = (CL.base[q] + c0 * CL.sz[q][0] * CL.sz[q][1]) * (int32_t)sizeof(float);
+    for (int ax = 0; ax < 3; ++ax)
+      inside_range((double)S.s[k], C.dir[c][ax], P.g[ax], &r.lo[ax], &r.hi[ax]);
+    zt[ck] = r;
+  }
+}
+
+// One (cone, sample) on level L for a thread's column: the planes' bilinear
+// values, then each voxel's z interpolation. Dm is the sample's weight D, or
+// 0 when the column is outside the grid in x or y.
+template <int L>
+__device__ inline void col_sample(const char* box, const ZRec& z, int32_t plane_bytes,
+                                  int32_t row_bytes, float wx, float wy, float Dm, int32_t vz0,
+                                  float occ[kColZ]) {
+  constexpr int R = col_planes<L>();
+  float pl[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const float* r0 = reinterpret_cast<const float*>(box + j * plane_bytes);
+    const float* r1 = reinterpret_cast<const float*>(box + j * plane_bytes + row_bytes);
+    const float a = __builtin_fmaf(wx, r0[1] - r0[0], r0[0]);
+    const float b = __builtin_fmaf(wx, r1[1] - r1[0], r1[0]);
+    pl[j] = __builtin_fmaf(wy, b - a, a);
+  }
+  float val[kColZ];
+#pragma unroll
+  for (int pz = 0; pz < kColZ; ++pz) {
+    constexpr int kMask = (1 << L) - 1;
+    const int ph = pz & kMask, i = pz >> L;
+    float p0 = pl[i], p1 = pl[i + 1];
+    if (L > 0 && ((z.delta >> ph) & 1)) {
+      p0 = pl[i + 1];
+      p1 = pl[(L > 0 ? i + 2 : i + 1)];
+    }
+    val[pz] = __builtin_fmaf(z.w[ph], p1 - p0, p0);
+  }
+  if (vz0 >= z.lo[2] && vz0 + kColZ - 1 <= z.hi[2]) {
+    // the common case: every voxel of the column segment is inside along z
+#pragma unroll
+    for (int pz = 0; pz < kColZ; ++pz) occ[pz] = __builtin_fmaf(val[pz], Dm, occ[pz]);
+  } else {
+#pragma unroll
+    for (int pz = 0; pz < kColZ; ++pz) {
+      const int32_t vz = vz0 + pz;
+      const float d = vz >= z.lo[2] && vz <= z.hi[2] ? Dm : 0.f;
+      occ[pz] = __builtin_fmaf(val[pz], d, occ[pz]);
+    }
+  }
+}
+
+// kN = S.n: the sample loop is unrolled, so the schedule's per-sample
+// constants stay in scalar registers for the whole block.
+template <int kN>
+__global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, Sched S,
+                                                           ColLevels CL,
+                                                           const ZRec* __restrict__ zt,
+                                                           const Tap* __restrict__ xyt,
+                                                           float* out) {
   extern __shared__ float lds[];
   // XCD x (= block mod 8) works through a contiguous run of tiles, so the
   // boxes neighbouring tiles share are fetched into one L2.
   const int b = blockIdx.x;
-  const int tile = (b % 8) * TL.tiles_per_xcd + b / 8;
-  const int nt = TL.tiles[0] * TL.tiles[1] * TL.tiles[2];
+  const int tile = (b % 8) * CL.tiles_per_xcd + b / 8;
+  const int nt = CL.tiles[0] * CL.tiles[1] * CL.tiles[2];
   if (tile >= nt) return;
-  const int32_t t0[3] = {kTile * (tile % TL.tiles[0]),
-                         kTile * ((tile / TL.tiles[0]) % TL.tiles[1]),
-                         kTile * (tile / (TL.tiles[0] * TL.tiles[1]))};
-  for (int q = 0; q < TL.n; ++q) {
-    const int lv = TL.lv[q], sz = TL.sz[q], n = sz * sz * sz;
-    const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
-    const int32_t o0 = (t0[0] >> lv) - TL.m[q], o1 = (t0[1] >> lv) - TL.m[q],
-                  o2 = (t0[2] >> lv) - TL.m[q];
-    const float* __restrict__ r = P.rho + P.off[lv];
-    float* box = lds + TL.base[q];
-    for (int i = threadIdx.x; i < n; i += kTileThreads) {
-      const int lx = i % sz, ly = (i / sz) % sz, lz = i / (sz * sz);
-      const int32_t x = min(max(o0 + lx, 0), dx - 1), y = min(max(o1 + ly, 0), dy - 1),
-                    z = min(max(o2 + lz, 0), dz - 1);
-      box[i] = r[(z * dy + y) * dx + x];
-    }
-  }
-  // tap tables (built once per launch by k_cone_table) into LDS
-  Tap* tab = reinterpret_cast<Tap*>(lds + TL.table);
+  const int32_t t0[3] = {kColX * (tile % CL.tiles[0]),
+                         kColY * ((tile / CL.tiles[0]) % CL.tiles[1]),
+                         kColZ * (tile / (CL.tiles[0] * CL.tiles[1]))};
+  // box copy: a half-wave per row, rows strided over the block's 8 half-waves
   {
-    const int n4 = C.n * kN * 24 / 2;   // two Taps per 16-byte word
-    const int4* src = reinterpret_cast<const int4*>(tab_g);
-    int4* dst = reinterpret_cast<int4*>(tab);
-    for (int e = threadIdx.x; e < n4; e += kTileThreads) dst[e] = src[e];
-  }
-  __syncthreads();
-  const float inv_n = 1.f / (float)C.n;
-  // per-sample constants, read once (wave-uniform, scalar registers)
-  int32_t kbase[kN], ksz[kN];
-  float kD[kN], ks[kN];
-#pragma unroll
-  for (int k = 0; k < kN; ++k) {
-    const int q = TL.slot[k];
-    kbase[k] = TL.base[q];
-    ksz[k] = TL.sz[q];
-    kD[k] = S.D[k];
-    ks[k] = S.s[k];
-  }
-#pragma unroll 1
-  for (int half = 0; half < kTile * kTile * kTile / kTileThreads; ++half) {
-    const int loc = threadIdx.x + half * kTileThreads;
-    const int32_t pl[3] = {loc & 7, (loc >> 3) & 7, loc >> 6};
-    const int32_t v[3] = {t0[0] + pl[0], t0[1] + pl[1], t0[2] + pl[2]};
-    if (v[0] >= P.g[0] || v[1] >= P.g[1] || v[2] >= P.g[2]) continue;
-    const bool near_face = near_any_face(P, v, S.reach);
-    float sum = 0.f;
-    const Tap* tc = tab;
-    for (int c = 0; c < C.n; ++c, tc += 24 * kN) {
-      float occ = 0.f;
-      bool go = true;
-#pragma unroll
-      for (int k = 0; k < kN; ++k) {
-        if (go && near_face) {
-          const double s = (double)ks[k];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const double x = ((double)v[a] + 0.5) + s * C.dir[c][a];
-            go &= x >= 0.0 && x < (double)P.g[a];
-          }
-        }
-        if (go) {
-          const Tap* tk = tc + 24 * k;
-          const Tap ex = tk[pl[0]], ey = tk[8 + pl[1]], ez = tk[16 + pl[2]];
-          const int sz = ksz[k], sz2 = sz * sz;
-          const float* bp = reinterpret_cast<const float*>(
-              reinterpret_cast<const char*>(lds + kbase[k]) + (ex.off + ey.off + ez.off));
-          // lerp(a, b, w) = a + w (b - a), fused
-          const float c00 = __builtin_fmaf(ex.w, bp[1] - bp[0], bp[0]);
-          const float c10 = __builtin_fmaf(ex.w, bp[sz + 1] - bp[sz], bp[sz]);
-          const float c01 = __builtin_fmaf(ex.w, bp[sz2 + 1] - bp[sz2], bp[sz2]);
-          const float c11 = __builtin_fmaf(ex.w, bp[sz2 + sz + 1] - bp[sz2 + sz], bp[sz2 + sz]);
-          const float c0 = __builtin_fmaf(ey.w, c10 - c00, c00);
-          const float c1 = __builtin_fmaf(ey.w, c11 - c01, c01);
-          occ = __builtin_fmaf(__builtin_fmaf(ez.w, c1 - c0, c0), kD[k], occ);
-          go = occ < 1.f;
+    const int xl = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+    for (int q = 0; q < CL.n; ++q) {
+      const int lv = CL.lv[q], sx = CL.sz[q][0], sy = CL.sz[q][1], sz = CL.sz[q][2];
+      const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
+      const int32_t o0 = (t0[0] >> lv) - CL.m[q], o1 = (t0[1] >> lv) - CL.m[q],
+                    o2 = (t0[2] >> lv) - CL.m[q];
+      const float* __restrict__ rho = P.rho + P.off[lv];
+      float* box = lds + CL.base[q];
+      int y = r0 % sy, zz = r0 / sy;
+      for (int r = r0; r < sy * sz; r += 8) {
+        const int32_t gy = min(max(o1 + y, 0), dy - 1), gz = min(max(o2 + zz, 0), dz - 1);
+        const float* src = rho + ((int64_t)gz * dy + gy) * dx;
+        float* dst = box + r * sx;
+        for (int x = xl; x < sx; x += 32) dst[x] = src[min(max(o0 + x, 0), dx - 1)];
+        y += 8;
+        while (y >= sy) {
+          y -= sy;
+          ++zz;
         }
       }
-      sum += occ < 1.f ? occ : 1.f;
     }
-    out[v[0] + (int64_t)P.g[0] * (v[1] + (int64_t)P.g[1] * v[2])] = 1.f - sum * inv_n;
   }
+  __syncthreads();
+  const int px = threadIdx.x & (kColX - 1), py = threadIdx.x / kColX;
+  const int32_t vx = t0[0] + px, vy = t0[1] + py;
+  const float inv_n = 1.f / (float)C.n;
+  float sum[kColZ];
+#pragma unroll
+  for (int i = 0; i < kColZ; ++i) sum[i] = 0.f;
+  const Tap* tc = xyt;
+  const ZRec* zc = zt;
+  for (int c = 0; c < C.n; ++c, tc += 32 * kN, zc += kN) {
+    float occ[kColZ];
+#pragma unroll
+    for (int i = 0; i < kColZ; ++i) occ[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kN; ++k) {
+      const ZRec z = zc[k];
+      const Tap tx = tc[32 * k + px], ty = tc[32 * k + 16 + py];
+      const bool in_xy = vx >= z.lo[0] && vx <= z.hi[0] && vy >= z.lo[1] && vy <= z.hi[1];
+      const float Dm = in_xy ? S.D[k] : 0.f;
+      const int q = CL.slot[k];
+      const int32_t row_bytes = CL.sz[q][0] * (int32_t)sizeof(float);
+      const int32_t plane_bytes = row_bytes * CL.sz[q][1];
+      const char* box = reinterpret_cast<const char*>(lds) + z.c0 + tx.off + ty.off;
+      switch (S.lv[k]) {
+        case 0: col_sample<0>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+        case 1: col_sample<1>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+        case 2: col_sample<2>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+        default: col_sample<3>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kColZ; ++i) sum[i] += occ[i] < 1.f ? occ[i] : 1.f;
+  }
+  if (vx >= P.g[0] || vy >= P.g[1]) return;
+  const int64_t col = vx + (int64_t)P.g[0] * vy, plane = (int64_t)P.g[0] * P.g[1];
+#pragma unroll
+  for (int i = 0; i < kColZ; ++i)
+    if (t0[2] + i < P.g[2]) out[col + plane * (t0[2] + i)] = 1.f - sum[i] * inv_n;
 }
 
 // Builds the schedule; fails (returns false) if it needs more than
@@ -345,11 +457,10 @@ Pyramid make_pyramid(const ls_lineset* s) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Boxes and tap tables of the tiled kernel for schedule S and n_cones cones;
-// false if a level above 3 is sampled or LDS would exceed the budget (then
-// the untiled kernels run).
-bool make_tile_levels(const ls_lineset* s, const Sched& S, int n_cones, TileLevels* T) {
-  *T = TileLevels{};
+// Boxes of the column kernel for schedule S; false if a level above 3 is
+// sampled or the boxes exceed the LDS budget (then the untiled kernels run).
+bool make_col_levels(const ls_lineset* s, const Sched& S, ColLevels* T) {
+  *T = ColLevels{};
   for (int k = 0; k < S.n; ++k) {
     const int lv = S.lv[k];
     if (lv > 3) return false;
@@ -364,51 +475,44 @@ bool make_tile_levels(const ls_lineset* s, const Sched& S, int n_cones, TileLeve
     T->m[q] = std::max(T->m[q], m);
     T->slot[k] = q;
   }
+  const int ext[3] = {kColX, kColY, kColZ};
   int64_t total = 0;
   for (int q = 0; q < T->n; ++q) {
-    const int ext = std::max(kTile >> T->lv[q], 1);
-    T->sz[q] = ext + 2 * T->m[q];
+    for (int a = 0; a < 3; ++a) T->sz[q][a] = std::max(ext[a] >> T->lv[q], 1) + 2 * T->m[q];
+    if (T->sz[q][2] < col_planes_rt(T->lv[q])) return false;
     T->base[q] = (int32_t)total;
-    total += (int64_t)T->sz[q] * T->sz[q] * T->sz[q];
+    total += (int64_t)T->sz[q][0] * T->sz[q][1] * T->sz[q][2];
   }
   T->base[T->n] = (int32_t)total;
-  total = (total + 3) & ~(int64_t)3;           // 16-byte alignment of the tables
-  T->table = (int32_t)total;
-  total += (int64_t)n_cones * S.n * 24 * 2;    // Tap = 2 floats
-  if (total * 4 > kTileLdsBytes) return false;
-  for (int a = 0; a < 3; ++a) T->tiles[a] = (s->grid[a] + kTile - 1) / kTile;
+  if (total * 4 > kColLdsBytes) return false;
+  for (int a = 0; a < 3; ++a) T->tiles[a] = (s->grid[a] + ext[a] - 1) / ext[a];
   const int64_t nt = (int64_t)T->tiles[0] * T->tiles[1] * T->tiles[2];
   T->tiles_per_xcd = (int32_t)((nt + 7) / 8);
   return true;
 }
 
-// LDS bytes of the tiled kernel's plan T.
-size_t tile_lds_bytes(const TileLevels& T, int n_cones, int n_samples) {
-  return sizeof(float) * ((size_t)T.table + (size_t)n_cones * n_samples * 24 * 2);
-}
-
 int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
                  bool ao) {
-  // the tiled kernel pays one LDS fill per tile; with few samples per voxel
+  // the column kernel pays one LDS fill per tile; with few samples per voxel
   // (the single shadow cone) direct gathers are cheaper
-  TileLevels T;
-  if (C.n >= 4 && S.n >= 1 && S.n <= kTileMaxSamples && make_tile_levels(s, S, C.n, &T)) {
-    const size_t lds = tile_lds_bytes(T, C.n, S.n);
-    const dim3 grid((unsigned)(8 * T.tiles_per_xcd)), block(kTileThreads);
+  ColLevels T;
+  if (C.n >= 4 && S.n >= 1 && S.n <= kColMaxSamples && make_col_levels(s, S, &T)) {
+    const size_t lds = sizeof(float) * (size_t)T.base[T.n];
+    const dim3 grid((unsigned)(8 * T.tiles_per_xcd)), block(kColThreads);
     const Pyramid P = make_pyramid(s);
-    // the tap tables: one small launch, then copied by every block
-    const size_t tab_bytes = sizeof(Tap) * (size_t)C.n * S.n * 24;
+    // the plane and tap tables: one small launch, read by every block
     int rc;
-    if (!s->cone_tab || s->cone_tab_bytes < tab_bytes) {
+    if (!s->cone_tab) {
       if ((rc = ls_alloc(s, &s->cone_tab, kMaxTabBytes))) return rc;
       s->cone_tab_bytes = kMaxTabBytes;
     }
-    Tap* tab = static_cast<Tap*>(s->cone_tab);
+    ZRec* zt = static_cast<ZRec*>(s->cone_tab);
+    Tap* xyt = reinterpret_cast<Tap*>(zt + (size_t)C.n * S.n);
     switch (S.n) {
 #define LS_CONES_CASE(N)                                                                        \
   case N:                                                                                       \
-    hipLaunchKernelGGL(k_cone_table<N>, dim3(1), block, 0, st, C, S, T, tab);                   \
-    hipLaunchKernelGGL(k_cones_tiled<N>, grid, block, lds, st, P, C, S, T, tab, out);          \
+    hipLaunchKernelGGL(k_col_table<N>, dim3(1), block, 0, st, P, C, S, T, zt, xyt);            \
+    hipLaunchKernelGGL(k_cones_col<N>, grid, block, lds, st, P, C, S, T, zt, xyt, out);        \
     break;
       LS_CONES_CASE(1) LS_CONES_CASE(2) LS_CONES_CASE(3) LS_CONES_CASE(4)
       LS_CONES_CASE(5) LS_CONES_CASE(6) LS_CONES_CASE(7) LS_CONES_CASE(8)

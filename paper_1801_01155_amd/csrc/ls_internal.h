@@ -47,7 +47,7 @@ struct ls_lineset {
   float* lod_rho;
   float* ao;
   float* sh;
-  void* cone_tab;         // tap tables of the tiled cone tracer
+  void* cone_tab;         // plane and tap tables of the column cone tracer
   size_t cone_tab_bytes;
   double lo_scale[4];
   size_t bytes;
