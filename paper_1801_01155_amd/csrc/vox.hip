@@ -71,30 +71,51 @@ __device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
 constexpr int kErrOffsets = 1;
 constexpr int kErrRange = 2;
 
-// floor(num / den) for 0 <= num <= 2^30, 0 < den < 2^31, quotient at most 256: an
-// fp32 estimate (relative error below 1e-6, so off by at most one) corrected
-// by one exact integer step either way.
-__device__ inline int32_t floor_div_small(int64_t num, int32_t den) {
+// Low 32 bits of a * b for a, b below 2^24: one full-rate 24-bit multiply
+// (written out because the operands' range is not visible to instruction
+// selection across basic blocks, which then picks the quarter-rate 32-bit one).
+__device__ inline uint32_t mul_lo24(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// floor(num / den) for 0 <= num <= 256 den, 0 < den < 2^18 (quotient at
+// most 256): an fp32 estimate (relative error below 1e-6, so off by at most
+// one) corrected by one exact step either way; 24-bit products.
+__device__ inline int32_t floor_div_small(int32_t num, int32_t den) {
+  __builtin_assume(den > 0 && den < (1 << 18));
   int32_t q = (int32_t)((float)num * __builtin_amdgcn_rcpf((float)den));
-  if ((int64_t)q * den > num) --q;
-  else if ((int64_t)(q + 1) * den <= num) ++q;
+  __builtin_assume(q >= 0 && q <= 512);
+  if ((int32_t)mul_lo24((uint32_t)q, (uint32_t)den) > num) --q;
+  else if ((int32_t)mul_lo24((uint32_t)(q + 1), (uint32_t)den) <= num) ++q;
   return q;
 }
 
+// Low 32 bits of the exact event point times den: P0 den + nf d, with
+// lattice coordinates and den below 2^18 (24-bit products, wrapping sum).
+__device__ inline void event_low(const int32_t P0[3], const int32_t d[3], int32_t den, int32_t nf,
+                                 uint32_t xl[3]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+    xl[b] = mul_lo24((uint32_t)P0[b], (uint32_t)den) + (uint32_t)__mul24(nf, d[b]);
+}
+
 // In-face bins of an event point on voxel `cell`, face normal `axis`.
-// xn = event point * den (exact), local coordinate = xn - 256 cell den in [0, 256 den].
-__device__ inline uint32_t face_code(int axis, int side, const int64_t xn[3], int64_t den,
+// xl = low 32 bits of (event point * den); the local coordinate
+// xn - 256 cell den lies in [0, 256 den] (below 2^26), so it is exact in
+// wrapping 32-bit arithmetic.
+__device__ inline uint32_t face_code(int axis, int side, const uint32_t xl[3], int32_t den,
                                      const int32_t cell[3], const GridArgs& ga) {
-  const int64_t x_u = axis == 0 ? xn[1] : xn[0];
-  const int64_t x_w = axis == 2 ? xn[1] : xn[2];
+  const uint32_t x_u = axis == 0 ? xl[1] : xl[0];
+  const uint32_t x_w = axis == 2 ? xl[1] : xl[2];
   const int32_t c_u = axis == 0 ? cell[1] : cell[0];
   const int32_t c_w = axis == 2 ? cell[1] : cell[2];
-  const int32_t den32 = (int32_t)den;                 // below 2^18
-  const int32_t step = den32 << ga.bin_shift;         // den * 256 / N, below 2^26
-  const int64_t lu = x_u - (int64_t)(c_u << 8) * den32;
-  const int64_t lw = x_w - (int64_t)(c_w << 8) * den32;
-  int32_t bu = floor_div_small(lu, step);
-  int32_t bw = floor_div_small(lw, step);
+  const int32_t lu = (int32_t)(x_u - mul_lo24((uint32_t)(c_u << 8), (uint32_t)den));
+  const int32_t lw = (int32_t)(x_w - mul_lo24((uint32_t)(c_w << 8), (uint32_t)den));
+  // bin = floor(l / (den 256 / N)) = floor(floor(l / 2^sh) / den), 256 / N = 2^sh
+  int32_t bu = floor_div_small(lu >> ga.bin_shift, den);
+  int32_t bw = floor_div_small(lw >> ga.bin_shift, den);
   bu = bu < ga.bins - 1 ? bu : ga.bins - 1;
   bw = bw < ga.bins - 1 ? bw : ga.bins - 1;
   return (uint32_t)(2 * axis + side) | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
@@ -145,15 +166,20 @@ __global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_
 }
 
 // An event: the curve crosses from `cell` into the next voxel at the exact
-// point xn / den (xn = point * den, den = |d| of the crossing axis).
+// segment parameter nf / den (den = |d| of the face axis, nf the numerator on
+// that axis), i.e. at the point xn / den with xn = P0 den + nf d.
 struct Ev {
-  int64_t xn[3];
-  int64_t den;
+  int32_t den, nf;
   uint32_t exit_code, entry_code;   // set when face codes are requested
   int fa, exit_side;                // face axis, side of the exited voxel's face
   int planes;                       // planes crossed at this event (1 to 3)
   int32_t ncell[3];                 // the entered voxel
 };
+
+// a * b for a, b below 2^24: two full-rate 24-bit multiplies.
+__device__ inline uint64_t mul_wide24(uint32_t a, uint32_t b) {
+  return (uint64_t)(a & 0xFFFFFFu) * (b & 0xFFFFFFu);
+}
 
 // Enumerates the events of segment P0 -> P1 in order: crossings of the
 // planes x_a = 256 k (up iff P0_a < 256k <= P1_a, down iff P1_a < 256k <=
@@ -162,49 +188,39 @@ struct Ev {
 template <bool kCodes, typename F>
 __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], const GridArgs& ga,
                                       F&& f) {
-  // lattice coordinates are below 2^18 (grid sides <= 1024), so plane
-  // offsets and differences fit 32 bits; products are formed in 64 bits
-  int32_t d[3], k[3];
-  int32_t left[3], cell[3];
-  int sg[3];
-  bool any = false;
+  // lattice coordinates are below 2^18 (grid sides <= 1024): differences,
+  // plane offsets and the numerators num_a = distance from P0 to the next
+  // plane along a (below 2^19) fit 24 bits, their cross products 48
+  int32_t d[3], dn[3], num[3], left[3], cell[3], sg[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     d[a] = P1[a] - P0[a];
     const int32_t c0 = P0[a] >> 8, c1 = P1[a] >> 8;
     cell[a] = c0;
     sg[a] = d[a] > 0 ? 1 : (d[a] < 0 ? -1 : 0);
-    k[a] = d[a] > 0 ? c0 + 1 : c0;
+    dn[a] = d[a] > 0 ? d[a] : -d[a];
+    num[a] = d[a] > 0 ? 256 * (c0 + 1) - P0[a] : P0[a] - 256 * c0;
     left[a] = abs(c1 - c0);
-    any |= left[a] != 0;
   }
-  while (any) {
-    int32_t num[3], dn[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      num[a] = sg[a] > 0 ? 256 * k[a] - P0[a] : P0[a] - 256 * k[a];
-      dn[a] = sg[a] > 0 ? d[a] : -d[a];
-    }
-    int best = -1;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (left[a] == 0) continue;
-      if (best < 0 || (int64_t)num[a] * dn[best] < (int64_t)num[best] * dn[a]) best = a;
-    }
+  while (left[0] + left[1] + left[2] > 0) {
+    // next crossing parameter of axis a: num_a / dn_a; compared exactly by
+    // cross products. grp: the axes whose next crossing is the earliest
+    // (several at once make one event; its face is the lowest axis's).
+    const uint64_t a01 = mul_wide24(num[0], dn[1]), a10 = mul_wide24(num[1], dn[0]);
+    const uint64_t a02 = mul_wide24(num[0], dn[2]), a20 = mul_wide24(num[2], dn[0]);
+    const uint64_t a12 = mul_wide24(num[1], dn[2]), a21 = mul_wide24(num[2], dn[1]);
+    const bool n0 = left[0] == 0, n1 = left[1] == 0, n2 = left[2] == 0;
     bool grp[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-      grp[a] = left[a] != 0 &&
-               (a == best || (int64_t)num[a] * dn[best] == (int64_t)num[best] * dn[a]);
+    grp[0] = !n0 && (n1 || a01 <= a10) && (n2 || a02 <= a20);
+    grp[1] = !n1 && (n0 || a10 <= a01) && (n2 || a12 <= a21);
+    grp[2] = !n2 && (n0 || a20 <= a02) && (n1 || a21 <= a12);
     const int fa = grp[0] ? 0 : (grp[1] ? 1 : 2);
     int32_t ncell[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) ncell[a] = cell[a] + (grp[a] ? sg[a] : 0);
     Ev ev;
-    ev.den = dn[fa];
-    const int32_t nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) ev.xn[b] = (int64_t)P0[b] * ev.den + (int64_t)nf * d[b];
+    ev.den = fa == 0 ? dn[0] : (fa == 1 ? dn[1] : dn[2]);
+    ev.nf = fa == 0 ? num[0] : (fa == 1 ? num[1] : num[2]);
     const int exit_side = (fa == 0 ? sg[0] : (fa == 1 ? sg[1] : sg[2])) > 0 ? 1 : 0;
     ev.fa = fa;
     ev.exit_side = exit_side;
@@ -212,19 +228,22 @@ __device__ inline void for_each_event(const int32_t P0[3], const int32_t P1[3], 
 #pragma unroll
     for (int b = 0; b < 3; ++b) ev.ncell[b] = ncell[b];
     if (kCodes) {
-      ev.exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, ga);
-      ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, ga);
+      uint32_t xl[3];
+      event_low(P0, d, ev.den, ev.nf, xl);
+      ev.exit_code = face_code(fa, exit_side, xl, ev.den, cell, ga);
+      // one plane crossed: the entered voxel has the same in-face cells, so
+      // the entry face has the exit face's bins and the other side
+      ev.entry_code = ev.planes == 1 ? ev.exit_code ^ 1u
+                                     : face_code(fa, 1 - exit_side, xl, ev.den, ncell, ga);
     }
     f(ev, cell);
-    any = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cell[a] = ncell[a];
       if (grp[a]) {
         --left[a];
-        k[a] += sg[a];
+        num[a] += 256;
       }
-      any |= left[a] != 0;
     }
   }
 }
@@ -293,7 +312,10 @@ __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
   out.xn1 = xn[1];
   out.xn2 = xn[2];
   out.den = den;
-  out.entry = face_code(fa, df > 0 ? 0 : 1, xn, den, c1, ga);
+  uint32_t xl[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) xl[b] = (uint32_t)xn[b];
+  out.entry = face_code(fa, df > 0 ? 0 : 1, xl, (int32_t)den, c1, ga);
   return cross;
 }
 
@@ -359,28 +381,35 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     // pass 2: emit the lines ending at this segment's events
     if (valid && e > 0) {
       uint64_t g = g0 + base;
-      Last prev = before;
+      bool has_prev = before.has != 0, first = true;
+      uint32_t prev_entry = before.entry;
       for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
-        if (prev.has) {
+        if (has_prev) {
           const uint64_t w = w0 + (g - 1);
           if (w < w_end) {
-            const bool same = prev.xn0 * ev.den == ev.xn[0] * prev.den &&
-                              prev.xn1 * ev.den == ev.xn[1] * prev.den &&
-                              prev.xn2 * ev.den == ev.xn[2] * prev.den;
-            if (!same && prev.entry != ev.exit_code) {
+            // events of one segment have distinct parameters, so only its
+            // first event can coincide with the event before it
+            bool same = false;
+            if (first) {
+              int64_t xn[3];
+#pragma unroll
+              for (int b = 0; b < 3; ++b)
+                xn[b] = (int64_t)P0[b] * ev.den + (int64_t)ev.nf * (P1[b] - P0[b]);
+              same = before.xn0 * ev.den == xn[0] * before.den &&
+                     before.xn1 * ev.den == xn[1] * before.den &&
+                     before.xn2 * ev.den == xn[2] * before.den;
+            }
+            if (!same && prev_entry != ev.exit_code) {
               const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
-              rec_out[w] = (uint64_t)prev.entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
+              rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
               vox_out[w] = vid;
               rank_out[w] = atomicAdd(hist + vid, 1u);
             }
           }
         }
-        prev.has = 1;
-        prev.xn0 = ev.xn[0];
-        prev.xn1 = ev.xn[1];
-        prev.xn2 = ev.xn[2];
-        prev.den = ev.den;
-        prev.entry = ev.entry_code;
+        has_prev = true;
+        first = false;
+        prev_entry = ev.entry_code;
         g += (uint64_t)ev.planes;
       });
     }
