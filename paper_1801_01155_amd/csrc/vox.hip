@@ -319,6 +319,21 @@ __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
   return cross;
 }
 
+// Segments with events wait in a per-wave ring in LDS until 64 of them
+// (or the curve's last ones) can be walked together, so the event walk runs
+// on full waves instead of on the lanes of each 64-segment chunk that happen
+// to cross a plane. An entry holds what the walk needs: the segment's
+// lattice end points, the curve's crossings before it and the event before
+// it (entry code and exact point; den = 0: none).
+constexpr int kEmitRing = 128;   // >= 2 * 64 - 1 pending entries
+struct EmitRing {
+  int32_t p[6][kEmitRing];
+  uint32_t g[kEmitRing];
+  uint32_t entry[kEmitRing];
+  int32_t den[kEmitRing];
+  long long x[3][kEmitRing];
+};
+
 // Lines of every curve in curve order: the line inside a voxel runs from
 // one event's entry point to the next event's exit point; it is dropped if
 // the two exact points or the two quantized endpoints coincide. The line
@@ -333,16 +348,66 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
                                                  const uint64_t* slot_off, uint64_t* rec_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
                                                  uint32_t* hist) {
+  __shared__ EmitRing rings[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (c >= n_curves) return;  // wave-uniform
+  EmitRing& Q = rings[threadIdx.x >> 6];
   const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
   const uint64_t w0 = slot_off[c], w_end = slot_off[c + 1];
   const uint64_t hi_bits =
       ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)(c & 0xFFFFFF) << 40);
   const int64_t gx = ga.g[0], gxy = (int64_t)ga.g[0] * ga.g[1];
+  const unsigned long long below = (1ull << lane) - 1ull;
+
+  // walks the first `count` ring entries from `head`, one per lane
+  auto walk = [&](uint32_t head, uint32_t count) {
+    // ring writes by other lanes of this wave precede these reads (LDS
+    // operations of a wave complete in order; the fence keeps the compiler
+    // from moving them)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if ((uint32_t)lane >= count) return;
+    const uint32_t k = (head + (uint32_t)lane) & (kEmitRing - 1);
+    const int32_t P0[3] = {Q.p[0][k], Q.p[1][k], Q.p[2][k]};
+    const int32_t P1[3] = {Q.p[3][k], Q.p[4][k], Q.p[5][k]};
+    const int32_t bden = Q.den[k];
+    const long long bx0 = Q.x[0][k], bx1 = Q.x[1][k], bx2 = Q.x[2][k];
+    uint64_t g = Q.g[k];
+    bool has_prev = bden != 0, first = true;
+    uint32_t prev_entry = Q.entry[k];
+    for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
+      if (has_prev) {
+        const uint64_t w = w0 + (g - 1);
+        if (w < w_end) {
+          // events of one segment have distinct parameters, so only its
+          // first event can coincide with the event before it
+          bool same = false;
+          if (first) {
+            int64_t xn[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+              xn[b] = (int64_t)P0[b] * ev.den + (int64_t)ev.nf * (P1[b] - P0[b]);
+            same = bx0 * ev.den == xn[0] * bden && bx1 * ev.den == xn[1] * bden &&
+                   bx2 * ev.den == xn[2] * bden;
+          }
+          if (!same && prev_entry != ev.exit_code) {
+            const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
+            rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
+            vox_out[w] = vid;
+            rank_out[w] = atomicAdd(hist + vid, 1u);
+          }
+        }
+      }
+      has_prev = true;
+      first = false;
+      prev_entry = ev.entry_code;
+      g += (uint64_t)ev.planes;
+    });
+  };
+
   Last carry{0, 0, 0, 0, 1, 0u};
-  uint64_t g0 = 0;  // events of the curve before this chunk
+  uint64_t g0 = 0;       // crossings of the curve before this chunk
+  uint32_t q_head = 0, q_n = 0;   // ring state (wave-uniform)
   for (int64_t s0 = v0; s0 + 1 < v1; s0 += 64) {
     const int64_t i = s0 + lane;
     const bool valid = i + 1 < v1;
@@ -351,9 +416,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
       load_vertex<kFloatIn>(xyz, lat, i, sa, P0);
       load_vertex<kFloatIn>(xyz, lat, i + 1, sa, P1);
     }
-    // pass 1: plane crossings and the last event. Lines are numbered by
-    // crossings (an event of k simultaneous planes uses k numbers), so the
-    // numbering needs no walk; the unused numbers stay invalid slots.
+    // plane crossings and the last event. Lines are numbered by crossings
+    // (an event of k simultaneous planes uses k numbers), so the numbering
+    // needs no walk; the unused numbers stay invalid slots.
     uint32_t e = 0;
     Last mine{0, 0, 0, 0, 1, 0u};
     if (valid) e = last_event(P0, P1, ga, mine);
@@ -378,47 +443,35 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     if (lane == 0) prev_src = -1;
     Last before = shfl_last(mine, prev_src >= 0 ? prev_src : 0);
     if (prev_src < 0) before = carry;
-    // pass 2: emit the lines ending at this segment's events
-    if (valid && e > 0) {
-      uint64_t g = g0 + base;
-      bool has_prev = before.has != 0, first = true;
-      uint32_t prev_entry = before.entry;
-      for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
-        if (has_prev) {
-          const uint64_t w = w0 + (g - 1);
-          if (w < w_end) {
-            // events of one segment have distinct parameters, so only its
-            // first event can coincide with the event before it
-            bool same = false;
-            if (first) {
-              int64_t xn[3];
+    // queue the segments with events
+    const bool act = valid && e > 0;
+    const unsigned long long am = __ballot(act);
+    if (act) {
+      const uint32_t k = (q_head + q_n + (uint32_t)__popcll(am & below)) & (kEmitRing - 1);
 #pragma unroll
-              for (int b = 0; b < 3; ++b)
-                xn[b] = (int64_t)P0[b] * ev.den + (int64_t)ev.nf * (P1[b] - P0[b]);
-              same = before.xn0 * ev.den == xn[0] * before.den &&
-                     before.xn1 * ev.den == xn[1] * before.den &&
-                     before.xn2 * ev.den == xn[2] * before.den;
-            }
-            if (!same && prev_entry != ev.exit_code) {
-              const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
-              rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
-              vox_out[w] = vid;
-              rank_out[w] = atomicAdd(hist + vid, 1u);
-            }
-          }
-        }
-        has_prev = true;
-        first = false;
-        prev_entry = ev.entry_code;
-        g += (uint64_t)ev.planes;
-      });
+      for (int a = 0; a < 3; ++a) {
+        Q.p[a][k] = P0[a];
+        Q.p[3 + a][k] = P1[a];
+      }
+      Q.g[k] = (uint32_t)(g0 + base);
+      Q.entry[k] = before.entry;
+      Q.den[k] = before.has ? (int32_t)before.den : 0;
+      Q.x[0][k] = before.xn0;
+      Q.x[1][k] = before.xn1;
+      Q.x[2][k] = before.xn2;
     }
+    q_n += (uint32_t)__popcll(am);
     // carry the chunk's last event
     const int last_src = __shfl(src, 63, 64);
     if (last_src >= 0) carry = shfl_last(mine, last_src);
     g0 += total;
+    if (q_n >= 64) {
+      walk(q_head, 64);
+      q_head = (q_head + 64) & (kEmitRing - 1);
+      q_n -= 64;
+    }
   }
-
+  if (q_n > 0) walk(q_head, q_n);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const uint32_t* rank,
