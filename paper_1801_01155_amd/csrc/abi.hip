@@ -292,19 +292,7 @@ int lineset_voxelize(const ls_voxelize_desc* d, void* hip_stream, ls_lineset_t* 
   s->n_curves = d->n_curves;
   s->n_vertices = d->n_vertices;
   s->device = dev;
-  SnapArgs sa{};
-  if (xyz) {
-    double lo[3], hi[3];
-    if ((rc = vox_bbox(xyz, d->n_vertices, lo, hi, st))) {
-      delete s;
-      return rc;
-    }
-    for (int a = 0; a < 3; ++a) sa.lo[a] = lo[a];
-    sa.scale = vox_scale(lo, hi, d->grid);
-    for (int a = 0; a < 3; ++a) s->lo_scale[a] = lo[a];
-    s->lo_scale[3] = sa.scale;
-  }
-  if ((rc = vox_build(s, xyz, lat, off, attr, sa, st))) {
+  if ((rc = vox_build(s, xyz, lat, off, attr, st))) {
     (void)hipStreamSynchronize(st);
     ls_free_all(s);
     delete s;

@@ -86,8 +86,10 @@ struct SnapArgs {
 int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream_t st);
 double vox_scale(const double lo[3], const double hi[3], const int32_t grid[3]);
 int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_t st);
+// Builds the set's CSR. Float input (xyz): the grid set-up runs on the
+// device and s->lo_scale is set; lattice input (lat): used as given.
 int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
-              const uint8_t* attr, SnapArgs sa, hipStream_t st);
+              const uint8_t* attr, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Density pyramid and illumination (lod.hip, illum.hip).

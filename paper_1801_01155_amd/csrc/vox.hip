@@ -70,6 +70,23 @@ __device__ inline bool in_range(const int32_t q[3], const GridArgs& ga) {
 // error codes written to err[0]
 constexpr int kErrOffsets = 1;
 constexpr int kErrRange = 2;
+constexpr int kErrNonFinite = 4;
+
+// Lattice scale 256 (G_a - 2) / extent_a, minimised over the axes with a
+// positive extent (0 if none): the grid set-up of section "Curve
+// voxelization", the same expression on the host and the device.
+__host__ __device__ inline double lattice_scale(const double lo[3], const double hi[3],
+                                                const int32_t grid[3]) {
+  double s = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    const double ext = hi[a] - lo[a];
+    if (ext > 0) {
+      const double cand = (256.0 * (double)(grid[a] - 2)) / ext;
+      if (cand < s) s = cand;
+    }
+  }
+  return s == INFINITY ? 0.0 : s;
+}
 
 // Low 32 bits of a * b for a, b below 2^24: one full-rate 24-bit multiply
 // (written out because the operands' range is not visible to instruction
@@ -130,9 +147,10 @@ constexpr int kWavesPerBlock = kBlock / 64;
 template <bool kFloatIn>
 __global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_t* lat,
                                                   const int64_t* curve_off, int64_t n_curves,
-                                                  int64_t n_vertices, SnapArgs sa, GridArgs ga,
-                                                  uint64_t* slots, int* err) {
+                                                  int64_t n_vertices, const SnapArgs* sap,
+                                                  GridArgs ga, uint64_t* slots, int* err) {
   const int lane = threadIdx.x & 63;
+  const SnapArgs sa = kFloatIn ? *sap : SnapArgs{};
   const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (c >= n_curves) return;  // wave-uniform
   const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
@@ -344,12 +362,14 @@ struct EmitRing {
 template <bool kFloatIn>
 __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
-                                                 int64_t n_curves, SnapArgs sa, GridArgs ga,
-                                                 const uint64_t* slot_off, uint64_t* rec_out,
+                                                 int64_t n_curves, const SnapArgs* sap,
+                                                 GridArgs ga, const uint64_t* slot_off,
+                                                 uint64_t* rec_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
                                                  uint32_t* hist) {
   __shared__ EmitRing rings[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
+  const SnapArgs sa = kFloatIn ? *sap : SnapArgs{};
   const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (c >= n_curves) return;  // wave-uniform
   EmitRing& Q = rings[threadIdx.x >> 6];
@@ -612,6 +632,50 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float* xyz, int64_t nv, d
     for (int a = 0; a < 6; ++a) part[6 * blockIdx.x + a] = s[a][0];
 }
 
+// Reduces k_bbox's per-block bounds and writes the lattice set-up; flags
+// non-finite input (bad, from k_bbox) in err.
+__global__ __launch_bounds__(kBlock) void k_lattice(const double* part, int blocks, int64_t nv,
+                                                    GridArgs ga, const int* bad, SnapArgs* out,
+                                                    int* err) {
+  __shared__ double s[6][kBlock];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < blocks; b += kBlock) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fmin(lo[a], part[6 * b + a]);
+      hi[a] = fmax(hi[a], part[6 * b + 3 + a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a][threadIdx.x] = lo[a];
+    s[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = fmin(s[a][threadIdx.x], s[a][threadIdx.x + st]);
+        s[3 + a][threadIdx.x] = fmax(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + st]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double l[3], h[3];
+    for (int a = 0; a < 3; ++a) {
+      l[a] = nv > 0 ? s[a][0] : 0.0;
+      h[a] = nv > 0 ? s[3 + a][0] : 0.0;
+    }
+    SnapArgs r;
+    for (int a = 0; a < 3; ++a) r.lo[a] = l[a];
+    r.scale = lattice_scale(l, h, ga.g);
+    *out = r;
+    if (*bad) atomicOr(err, kErrNonFinite);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_snap(const float* xyz, int64_t nv, SnapArgs sa,
                                                  int32_t* lat) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -683,16 +747,7 @@ int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream
 }
 
 double vox_scale(const double lo[3], const double hi[3], const int32_t grid[3]) {
-  double s = INFINITY;
-  for (int a = 0; a < 3; ++a) {
-    volatile double ext = hi[a] - lo[a];
-    if (ext > 0) {
-      volatile double num = 256.0 * (double)(grid[a] - 2);
-      volatile double cand = num / ext;
-      if (cand < s) s = cand;
-    }
-  }
-  return std::isinf(s) ? 0.0 : s;
+  return lattice_scale(lo, hi, grid);
 }
 
 int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_t st) {
@@ -703,7 +758,7 @@ int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_
 }
 
 int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
-              const uint8_t* attr, SnapArgs sa, hipStream_t st) {
+              const uint8_t* attr, hipStream_t st) {
   GridArgs ga;
   for (int a = 0; a < 3; ++a) ga.g[a] = s->grid[a];
   ga.bins = s->bins;
@@ -714,19 +769,33 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   const bool float_in = xyz != nullptr;
   int rc;
 
-  // 1. per-curve slot counts + validation
-  DeviceBuf slots(st), err(st), sums64(st);
-  if ((rc = slots.alloc(sizeof(uint64_t) * (C + 1))) || (rc = err.alloc(sizeof(int))) ||
-      (rc = sums64.alloc(sizeof(uint64_t) * scan_block_sums_len(C))))
+  // 0. float input: grid set-up on the device (bounds, then the lattice
+  //    scale), read back with the slot count below
+  const int64_t nv = s->n_vertices;
+  const int bb_blocks = (int)std::min<int64_t>(std::max<int64_t>((nv + kBlock - 1) / kBlock, 1), 1024);
+  DeviceBuf slots(st), err(st), sums64(st), lattice(st);
+  if ((rc = slots.alloc(sizeof(uint64_t) * (C + 1))) || (rc = err.alloc(2 * sizeof(int))) ||
+      (rc = sums64.alloc(sizeof(uint64_t) * scan_block_sums_len(C))) ||
+      (rc = lattice.alloc(sizeof(SnapArgs) + sizeof(double) * 6 * bb_blocks)))
     return rc;
-  LS_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  LS_HIP(hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
+  SnapArgs* sad = lattice.as<SnapArgs>();
+  if (float_in) {
+    double* part = reinterpret_cast<double*>(sad + 1);
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv, part,
+                       err.as<int>() + 1);
+    hipLaunchKernelGGL(k_lattice, dim3(1), dim3(kBlock), 0, st, part, bb_blocks, nv, ga,
+                       err.as<int>() + 1, sad, err.as<int>());
+    LS_HIP(hipGetLastError());
+  }
+  // 1. per-curve slot counts + validation
   if (C > 0) {
     if (float_in)
       hipLaunchKernelGGL((k_count<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
+                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), err.as<int>());
     else
       hipLaunchKernelGGL((k_count<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, C, s->n_vertices, sa, ga, slots.as<uint64_t>(), err.as<int>());
+                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), err.as<int>());
     LS_HIP(hipGetLastError());
   }
   if ((rc = exclusive_scan_u64(slots.as<uint64_t>(), slots.as<uint64_t>(), C, sums64.as<uint64_t>(),
@@ -734,10 +803,20 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
     return rc;
   uint64_t n_slots = 0;
   int herr = 0;
+  SnapArgs hsa{};
   LS_HIP(hipMemcpyAsync(&n_slots, slots.as<uint64_t>() + C, sizeof(uint64_t),
                         hipMemcpyDeviceToHost, st));
   LS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (float_in) LS_HIP(hipMemcpyAsync(&hsa, sad, sizeof(SnapArgs), hipMemcpyDeviceToHost, st));
   LS_HIP(hipStreamSynchronize(st));
+  if (herr & kErrNonFinite) {
+    ls_set_error("non-finite vertex coordinate");
+    return LS_EINVAL;
+  }
+  if (float_in) {
+    for (int a = 0; a < 3; ++a) s->lo_scale[a] = hsa.lo[a];
+    s->lo_scale[3] = hsa.scale;
+  }
   if (herr & kErrOffsets) {
     ls_set_error("curve_off must start at 0, be non-decreasing and end at most at n_vertices");
     return LS_EINVAL;
@@ -766,11 +845,11 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   if (C > 0) {
     if (float_in)
       hipLaunchKernelGGL((k_emit<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         curve_off, attr, C, sad, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     else
       hipLaunchKernelGGL((k_emit<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, sa, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         curve_off, attr, C, sad, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     LS_HIP(hipGetLastError());
   }

@@ -37,6 +37,20 @@ def test_voxelize_small_workload_from_xyz():
     info = s.info()
     cnt = np.diff(ref.offsets.astype(np.int64))
     assert info.nonempty_voxels == int((cnt > 0).sum()) and info.max_list == int(cnt.max())
+    # the grid set-up made on the device during voxelization (bounds, scale)
+    _, lo, sc = O.grid_setup(ls.xyz, (w["grid"],) * 3)
+    assert list(info.lo_scale) == list(lo) + [sc]
+
+
+def test_voxelize_xyz_degenerate_and_non_finite():
+    # one vertex (zero extent: scale 0), and a non-finite coordinate (rejected)
+    one = np.array([[0.25, -1.0, 3.0]], np.float32)
+    s = L.lineset_voxelize(np.array([0, 1], np.int64), (8, 8, 8), 32, xyz=one)
+    _, lo, sc = O.grid_setup(one, (8, 8, 8))
+    assert s.info().n_records == 0 and list(s.info().lo_scale) == list(lo) + [sc]
+    bad = np.array([[0.0, 0.0, 0.0], [1.0, np.nan, 0.0], [2.0, 1.0, 0.5]], np.float32)
+    with pytest.raises(L.LinesetError):
+        L.lineset_voxelize(np.array([0, 3], np.int64), (8, 8, 8), 32, xyz=bad)
 
 
 @pytest.mark.parametrize("seed,step,bins", [(1, 64, 4), (2, 32, 32), (3, 1, 8), (4, 128, 64),
