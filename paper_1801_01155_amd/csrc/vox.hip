@@ -494,14 +494,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
   if (q_n > 0) walk(q_head, q_n);
 }
 
+// Each emitted line e of voxel v goes to slot offsets[v] + rank[e] of its
+// voxel's range, as the pair (v, e): one 8-byte write, so the rank pass reads
+// the voxel with the index instead of gathering it.
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const uint32_t* rank,
                                                     int64_t n_slots, const uint32_t* offsets,
-                                                    uint32_t* idx) {
+                                                    uint64_t* idx) {
   int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n_slots) return;
   uint32_t v = vox[e];
   if (v == LS_INVALID_VOXEL) return;
-  idx[offsets[v] + rank[e]] = (uint32_t)e;
+  idx[offsets[v] + rank[e]] = ((uint64_t)v << 32) | (uint32_t)e;
 }
 
 // Each CSR slot p holds some emitted line e of voxel v; its final position is
@@ -511,9 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const u
 // in LDS when they fit, else counted from memory.
 constexpr int kRankLds = 4096;
 
-__global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint32_t* vox,
-                                                 const uint64_t* rec, int64_t n_records,
-                                                 const uint32_t* offsets, uint64_t* records) {
+__global__ __launch_bounds__(kBlock) void k_rank(const uint64_t* idx, const uint64_t* rec,
+                                                 int64_t n_records, const uint32_t* offsets,
+                                                 uint64_t* records) {
   __shared__ uint32_t s_idx[kRankLds];
   __shared__ uint32_t s_range[2];
   const int64_t p0 = (int64_t)blockIdx.x * kBlock;
@@ -521,8 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint
   const int64_t n_here = n_records - p0 < kBlock ? n_records - p0 : kBlock;
   uint32_t e = 0, lo = 0, hi = 0;
   if (p < n_records) {
-    e = idx[p];
-    const uint32_t v = vox[e];
+    const uint64_t ve = idx[p];
+    e = (uint32_t)ve;
+    const uint32_t v = (uint32_t)(ve >> 32);
     lo = offsets[v];
     hi = offsets[v + 1];
   }
@@ -532,14 +536,14 @@ __global__ __launch_bounds__(kBlock) void k_rank(const uint32_t* idx, const uint
   const uint32_t blo = s_range[0], bhi = s_range[1];
   const bool staged = bhi - blo <= (uint32_t)kRankLds;   // block-uniform
   if (staged)
-    for (uint32_t q = blo + threadIdx.x; q < bhi; q += kBlock) s_idx[q - blo] = idx[q];
+    for (uint32_t q = blo + threadIdx.x; q < bhi; q += kBlock) s_idx[q - blo] = (uint32_t)idx[q];
   __syncthreads();
   if (p >= n_records) return;
   uint32_t r = 0;
   if (staged) {
     for (uint32_t q = lo; q < hi; ++q) r += s_idx[q - blo] < e;
   } else {
-    for (uint32_t q = lo; q < hi; ++q) r += idx[q] < e;
+    for (uint32_t q = lo; q < hi; ++q) r += (uint32_t)idx[q] < e;
   }
   records[lo + r] = rec[e];
 }
@@ -865,17 +869,16 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   // 5. scatter + rank/gather into the set's record array
   if ((rc = ls_alloc(s, (void**)&s->records, sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
   DeviceBuf idx(st);
-  if ((rc = idx.alloc(sizeof(uint32_t) * (n_rec ? n_rec : 1)))) return rc;
+  if ((rc = idx.alloc(sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
   if (n_slots > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for((int64_t)n_slots)), dim3(kBlock), 0, st,
                        vox.as<uint32_t>(), rank.as<uint32_t>(), (int64_t)n_slots, s->offsets,
-                       idx.as<uint32_t>());
+                       idx.as<uint64_t>());
     LS_HIP(hipGetLastError());
   }
   if (n_rec > 0) {
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(n_rec)), dim3(kBlock), 0, st, idx.as<uint32_t>(),
-                       vox.as<uint32_t>(), rec.as<uint64_t>(), (int64_t)n_rec, s->offsets,
-                       s->records);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(n_rec)), dim3(kBlock), 0, st, idx.as<uint64_t>(),
+                       rec.as<uint64_t>(), (int64_t)n_rec, s->offsets, s->records);
     LS_HIP(hipGetLastError());
   }
 
