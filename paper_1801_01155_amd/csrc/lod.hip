@@ -1,6 +1,6 @@
 // Density pyramid (section "LoD construction") on gfx950.
 //
-// Level 0, one thread per voxel over its contiguous line list:
+// Level 0 over each voxel's contiguous line list:
 //   count = #lines, len = sum |exit - entry|, rho = sum |exit - entry| * sigma
 // (sigma = lut[attr].a, or 1 for opaque lines). Each coarser level averages
 // the 2^3 children of the finer one (children beyond an odd side count as 0).
@@ -23,26 +23,80 @@ __device__ inline void decode_point(uint32_t code, float inv_bins, float p[3]) {
   p[2] = axis == 2 ? side : w;
 }
 
+// Level 0, a wave per 64 consecutive voxels. Their lists are one contiguous
+// run of records, read 64 at a time by the whole wave (coalesced); each
+// line's length goes through a segmented scan over the lanes holding its
+// voxel's lines, and the voxel's lane collects its segment's total. A wave
+// costs (lines of its voxels) / 64 steps instead of its longest list.
+__device__ inline int wave_lane() { return (int)(threadIdx.x & 63); }
+
 __global__ __launch_bounds__(kBlock) void k_lod0(const uint32_t* offsets, const uint64_t* records,
                                                  int64_t nvox, float inv_bins, const float* lut,
                                                  int opaque, float* count, float* len, float* rho) {
-  int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (v >= nvox) return;
-  uint32_t lo = offsets[v], hi = offsets[v + 1];
-  float c = 0.f, l = 0.f, r = 0.f;
-  for (uint32_t k = lo; k < hi; ++k) {
-    uint64_t rec = records[k];
-    float a[3], b[3];
-    decode_point((uint32_t)(rec & 0x7FFFu), inv_bins, a);
-    decode_point((uint32_t)((rec >> 15) & 0x7FFFu), inv_bins, b);
-    float dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-    float L = sqrtf(dx * dx + dy * dy + dz * dz);
-    float sigma = opaque ? 1.f : lut[4 * ((rec >> 32) & 0xFF) + 3];
-    c += 1.f;
-    l += L;
-    r += L * sigma;
+  const int lane = wave_lane();
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = v < nvox;
+  uint32_t lo = 0, hi = 0;
+  if (in) {
+    lo = offsets[v];
+    hi = offsets[v + 1];
   }
-  count[v] = c;
+  const uint32_t n = hi - lo;
+  // exclusive scan of the list lengths: this voxel's lines are the wave's
+  // lines [P, P + n), i.e. records lo0 + [P, P + n)
+  uint32_t inc = n;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  const uint32_t P = inc - n;
+  const uint32_t N = __shfl(inc, 63, 64);
+  const uint32_t lo0 = __shfl(lo, 0, 64);
+  float l = 0.f, r = 0.f;
+  for (uint32_t base = 0; base < N; base += 64) {
+    const uint32_t w = base + (uint32_t)lane;
+    // owner: the last lane whose P <= w (lists are in lane order)
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t pq = __shfl(P, o + step, 64);
+      if (pq <= w) o += step;
+    }
+    float L = 0.f, Ls = 0.f;
+    if (w < N) {
+      const uint64_t rec = records[lo0 + w];
+      float a[3], b[3];
+      decode_point((uint32_t)(rec & 0x7FFFu), inv_bins, a);
+      decode_point((uint32_t)((rec >> 15) & 0x7FFFu), inv_bins, b);
+      const float dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+      L = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float sigma = opaque ? 1.f : lut[4 * ((rec >> 32) & 0xFF) + 3];
+      Ls = L * sigma;
+    }
+    // segmented inclusive scan: lanes of one owner form a contiguous run
+    const uint32_t po = __shfl(P, o, 64);
+    const int seg0 = po > base ? (int)(po - base) : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float yl = __shfl_up(L, d, 64), yr = __shfl_up(Ls, d, 64);
+      if (lane - d >= seg0) {
+        L += yl;
+        Ls += yr;
+      }
+    }
+    // this voxel's run in the chunk ends at lane min(P + n, base + 64) - 1
+    // (all lanes shuffle; lanes without a run here discard the value)
+    const bool here = n != 0 && P < base + 64u && P + n > base;
+    const int end = here ? (int)((P + n < base + 64u ? P + n : base + 64u) - 1u - base) : 0;
+    const float tl = __shfl(L, end, 64), tr = __shfl(Ls, end, 64);
+    if (here) {
+      l += tl;
+      r += tr;
+    }
+  }
+  if (!in) return;
+  count[v] = (float)n;
   len[v] = l;
   rho[v] = r;
 }
