@@ -338,8 +338,13 @@ int lineset_build_lod(ls_lineset_t s, const ls_lod_desc* d, void* hip_stream) {
   int rc;
   if ((rc = lod_build(s, d->lut_rgba, d->opaque, st))) return rc;
   if (d->build_ao && d->build_shadow) {
-    // The shadow cone (latency-bound gathers) runs on a second stream beside
-    // the AO cones (VALU-bound), both after the pyramid, joined before return.
+    bool applied = false;
+    if ((rc = illum_ao_shadow(s, d->ao_cones, d->ao_radius, d->light_dir, d->cone_aperture, st,
+                              &applied)))
+      return rc;
+    if (applied) return LS_OK;
+    // Otherwise the shadow cone (latency-bound gathers) runs on a second
+    // stream beside the AO cones, both after the pyramid, joined before return.
     SideStream* side = side_stream(s->device);
     if (!side) return LS_EDEVICE;
     std::lock_guard<std::mutex> lk(side->mu);

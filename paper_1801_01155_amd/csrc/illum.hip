@@ -334,13 +334,18 @@ __device__ inline void col_sample(const char* box, const ZRec& z, int32_t plane_
 }
 
 // kN = S.n: the sample loop is unrolled, so the schedule's per-sample
-// constants stay in scalar registers for the whole block.
-template <int kN>
+// constants stay in scalar registers for the whole block. With kShadow the
+// last cone of C is the shadow cone: its first kN samples are the AO
+// schedule's (same distances, diameters and levels, so the same boxes) and
+// are traced like the AO cones; its remaining samples SH[kN..) lie on
+// levels >= 3 and are interpolated per column (see below). AO averages the
+// other C.n - 1 cones.
+template <int kN, bool kShadow>
 __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, Sched S,
                                                            ColLevels CL,
                                                            const ZRec* __restrict__ zt,
                                                            const Tap* __restrict__ xyt,
-                                                           float* out) {
+                                                           float* out, Sched SH, float* sh_out) {
   extern __shared__ float lds[];
   // XCD x (= block mod 8) works through a contiguous run of tiles, so the
   // boxes neighbouring tiles share are fetched into one L2.
@@ -378,14 +383,15 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
   __syncthreads();
   const int px = threadIdx.x & (kColX - 1), py = threadIdx.x / kColX;
   const int32_t vx = t0[0] + px, vy = t0[1] + py;
-  const float inv_n = 1.f / (float)C.n;
+  const int n_ao = kShadow ? C.n - 1 : C.n;
+  const float inv_n = 1.f / (float)n_ao;
   float sum[kColZ];
 #pragma unroll
   for (int i = 0; i < kColZ; ++i) sum[i] = 0.f;
-  const Tap* tc = xyt;
-  const ZRec* zc = zt;
-  for (int c = 0; c < C.n; ++c, tc += 32 * kN, zc += kN) {
-    float occ[kColZ];
+  float occ[kColZ];
+  for (int c = 0; c < C.n; ++c) {
+    const Tap* tc = xyt + 32 * kN * c;
+    const ZRec* zc = zt + kN * c;
 #pragma unroll
     for (int i = 0; i < kColZ; ++i) occ[i] = 0.f;
 #pragma unroll
@@ -405,6 +411,7 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
         default: col_sample<3>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
       }
     }
+    if (kShadow && c == n_ao) break;   // the shadow cone's occ stays in occ[]
 #pragma unroll
     for (int i = 0; i < kColZ; ++i) sum[i] += occ[i] < 1.f ? occ[i] : 1.f;
   }
@@ -413,6 +420,85 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
 #pragma unroll
   for (int i = 0; i < kColZ; ++i)
     if (t0[2] + i < P.g[2]) out[col + plane * (t0[2] + i)] = 1.f - sum[i] * inv_n;
+  if (kShadow) {
+    // The shadow cone's coarse samples (levels >= 3, the schedule's tail):
+    // the column's 8 voxels share their x and y taps, and their level-z
+    // cells c(pz) = (vz >> l) + floor(z) span at most two neighbours, so a
+    // sample costs the (x, y) bilinear values of three planes (paired x
+    // loads, clamp to edge as in sample()) and one z interpolation per
+    // voxel, in sample()'s order. Outside samples add nothing (every later
+    // one is outside too); saturation is applied at the end.
+    const double* u = C.dir[n_ao];
+    const float u32[3] = {(float)u[0], (float)u[1], (float)u[2]};
+    for (int k = kN; k < SH.n; ++k) {
+      const int lv = SH.lv[k];
+      const float sk = SH.s[k], Dk = SH.D[k];
+      const float scale = __builtin_ldexpf(1.0f, -lv);
+      const int32_t mask = (1 << lv) - 1;
+      const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
+      // x and y taps of the column
+      const float fx = 0.5f + sk * u32[0], fy = 0.5f + sk * u32[1], fz = 0.5f + sk * u32[2];
+      const float xx = ((float)(vx & mask) + fx) * scale - 0.5f;
+      const float xy = ((float)(vy & mask) + fy) * scale - 0.5f;
+      const float flx = floorf(xx), fly = floorf(xy);
+      const float frx = xx - flx, fry = xy - fly;
+      const int32_t i0x = (vx >> lv) + (int32_t)flx, i0y = (vy >> lv) + (int32_t)fly;
+      const int32_t y0 = min(max(i0y, 0), dy - 1), y1 = min(max(i0y + 1, 0), dy - 1);
+      int32_t jx = 0;
+      float wx = 0.f;
+      if (dx >= 2) {
+        jx = min(max(i0x, 0), dx - 2);
+        wx = fminf(fmaxf((float)(i0x - jx) + frx, 0.f), 1.f);
+      }
+      // inside the grid in x and y (fp64, the definition's expression)
+      const double ax = ((double)vx + 0.5) + (double)sk * u[0];
+      const double ay = ((double)vy + 0.5) + (double)sk * u[1];
+      const bool in_xy = ax >= 0.0 && ax < (double)P.g[0] && ay >= 0.0 && ay < (double)P.g[1];
+      // z cells of the column's voxels: c(0) <= c(pz) <= c(0) + 1
+      float frz[kColZ];
+      int32_t iz0[kColZ];
+#pragma unroll
+      for (int i = 0; i < kColZ; ++i) {
+        const int32_t vz = t0[2] + i;
+        const float zz = ((float)(vz & mask) + fz) * scale - 0.5f;
+        const float flz = floorf(zz);
+        frz[i] = zz - flz;
+        iz0[i] = (vz >> lv) + (int32_t)flz;
+      }
+      const float* __restrict__ r = P.rho + P.off[lv];
+      float pl[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int32_t zj = min(max(iz0[0] + j, 0), dz - 1);
+        const int32_t r0 = (y0 + dy * zj) * dx, r1 = (y1 + dy * zj) * dx;
+        float c0, c1;
+        if (dx >= 2) {
+          float2 a, b;
+          __builtin_memcpy(&a, r + r0 + jx, sizeof(a));
+          __builtin_memcpy(&b, r + r1 + jx, sizeof(b));
+          c0 = __builtin_fmaf(wx, a.y - a.x, a.x);
+          c1 = __builtin_fmaf(wx, b.y - b.x, b.x);
+        } else {
+          c0 = r[r0];
+          c1 = r[r1];
+        }
+        pl[j] = __builtin_fmaf(fry, c1 - c0, c0);
+      }
+      const double bz = (double)sk * u[2];
+#pragma unroll
+      for (int i = 0; i < kColZ; ++i) {
+        const bool up = iz0[i] != iz0[0];
+        const float p0 = up ? pl[1] : pl[0], p1 = up ? pl[2] : pl[1];
+        const float val = __builtin_fmaf(frz[i], p1 - p0, p0);
+        const double az = ((double)(t0[2] + i) + 0.5) + bz;
+        const bool in = in_xy && az >= 0.0 && az < (double)P.g[2];
+        occ[i] = in ? __builtin_fmaf(val, Dk, occ[i]) : occ[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kColZ; ++i)
+      if (t0[2] + i < P.g[2]) sh_out[col + plane * (t0[2] + i)] = 1.f - (occ[i] < 1.f ? occ[i] : 1.f);
+  }
 }
 
 // Builds the schedule; fails (returns false) if it needs more than
@@ -491,8 +577,12 @@ bool make_col_levels(const ls_lineset* s, const Sched& S, ColLevels* T) {
   return true;
 }
 
+// Column kernel when it applies, else the per-voxel kernels (ao: k_ao, else
+// k_shadow). With sh_out, C's last cone is the shadow cone with schedule SH
+// (see k_cones_col); the call then fails with LS_EUNSUPPORTED instead of
+// falling back when the column kernel does not apply.
 int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipStream_t st,
-                 bool ao) {
+                 bool ao, const Sched* SH = nullptr, float* sh_out = nullptr) {
   // the column kernel pays one LDS fill per tile; with few samples per voxel
   // (the single shadow cone) direct gathers are cheaper
   ColLevels T;
@@ -512,12 +602,19 @@ int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipS
 #define LS_CONES_CASE(N)                                                                        \
   case N:                                                                                       \
     hipLaunchKernelGGL(k_col_table<N>, dim3(1), block, 0, st, P, C, S, T, zt, xyt);            \
-    hipLaunchKernelGGL(k_cones_col<N>, grid, block, lds, st, P, C, S, T, zt, xyt, out);        \
+    if (sh_out)                                                                                 \
+      hipLaunchKernelGGL((k_cones_col<N, true>), grid, block, lds, st, P, C, S, T, zt, xyt,    \
+                         out, *SH, sh_out);                                                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_cones_col<N, false>), grid, block, lds, st, P, C, S, T, zt, xyt,   \
+                         out, S, nullptr);                                                      \
     break;
       LS_CONES_CASE(1) LS_CONES_CASE(2) LS_CONES_CASE(3) LS_CONES_CASE(4)
       LS_CONES_CASE(5) LS_CONES_CASE(6) LS_CONES_CASE(7) LS_CONES_CASE(8)
 #undef LS_CONES_CASE
     }
+  } else if (sh_out) {
+    return LS_EUNSUPPORTED;
   } else if (ao) {
     hipLaunchKernelGGL(k_ao, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, make_pyramid(s), C,
                        S, s->nvox, out);
@@ -531,18 +628,15 @@ int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipS
 
 }  // namespace
 
-int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st) {
-  if (n_cones < 1 || n_cones > kMaxCones) {
-    ls_set_error("ao_cones must be in [1, %d]", kMaxCones);
-    return LS_EINVAL;
-  }
-  int rc;
-  if (!s->ao && (rc = ls_alloc(s, (void**)&s->ao, sizeof(float) * (size_t)s->nvox))) return rc;
+namespace {
+
+// AO cone set: spherical Fibonacci directions z_i = 1 - (2i + 1)/n, azimuth
+// i * pi (3 - sqrt 5).
+Cones ao_cones(int n_cones, float radius, float aperture) {
   Cones C{};
   C.n = n_cones;
   C.s_max = (double)radius;
   C.aperture = (double)aperture;
-  // spherical Fibonacci directions: z_i = 1 - (2i + 1)/n, azimuth i * pi (3 - sqrt 5)
   const double ga = 3.14159265358979323846 * (3.0 - std::sqrt(5.0));
   for (int i = 0; i < n_cones; ++i) {
     double z = 1.0 - (2.0 * i + 1.0) / (double)n_cones;
@@ -552,6 +646,46 @@ int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream
     C.dir[i][1] = r * std::sin(ph);
     C.dir[i][2] = z;
   }
+  return C;
+}
+
+}  // namespace
+
+int illum_ao_shadow(ls_lineset* s, int n_cones, float radius, const float light[3],
+                    float aperture, hipStream_t st, bool* applied) {
+  *applied = false;
+  if (n_cones < 1 || n_cones + 1 > kMaxCones) return LS_OK;
+  Sched S, SH;
+  if (!make_sched(s, (double)radius, (double)aperture, &S) ||
+      !make_sched(s, INFINITY, (double)aperture, &SH) || SH.n < S.n)
+    return LS_OK;
+  for (int k = 0; k < S.n; ++k)
+    if (SH.s[k] != S.s[k] || SH.D[k] != S.D[k] || SH.lv[k] != S.lv[k]) return LS_OK;
+  // the column kernel's shadow tail takes samples on levels >= 3 (a column's
+  // 8 voxels then span at most two level cells along z)
+  for (int k = S.n; k < SH.n; ++k)
+    if (SH.lv[k] < 3) return LS_OK;
+  ColLevels T;
+  if (S.n < 1 || S.n > kColMaxSamples || !make_col_levels(s, S, &T)) return LS_OK;
+  int rc;
+  if (!s->ao && (rc = ls_alloc(s, (void**)&s->ao, sizeof(float) * (size_t)s->nvox))) return rc;
+  if (!s->sh && (rc = ls_alloc(s, (void**)&s->sh, sizeof(float) * (size_t)s->nvox))) return rc;
+  Cones C = ao_cones(n_cones, radius, aperture);
+  for (int a = 0; a < 3; ++a) C.dir[n_cones][a] = (double)light[a];
+  C.n = n_cones + 1;
+  if ((rc = launch_cones(s, C, S, s->ao, st, true, &SH, s->sh))) return rc;
+  *applied = true;
+  return LS_OK;
+}
+
+int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st) {
+  if (n_cones < 1 || n_cones > kMaxCones) {
+    ls_set_error("ao_cones must be in [1, %d]", kMaxCones);
+    return LS_EINVAL;
+  }
+  int rc;
+  if (!s->ao && (rc = ls_alloc(s, (void**)&s->ao, sizeof(float) * (size_t)s->nvox))) return rc;
+  const Cones C = ao_cones(n_cones, radius, aperture);
   Sched S;
   if (!make_sched(s, (double)radius, (double)aperture, &S)) {
     ls_set_error("cone schedule longer than %d samples or not exact in fp32 (aperture too small?)",

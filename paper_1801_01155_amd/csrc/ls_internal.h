@@ -96,6 +96,11 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
 void lod_plan(const int32_t grid[3], int32_t* n_levels, int32_t dims[][3], int64_t* level_off);
 int lod_build(ls_lineset* s, const float* lut, int opaque, hipStream_t st);
 int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st);
+// Both grids in one pass of the column cone tracer (the shadow cone rides
+// along with the AO cones) when the schedules allow it; *applied = false
+// (nothing launched) otherwise.
+int illum_ao_shadow(ls_lineset* s, int n_cones, float radius, const float light[3],
+                    float aperture, hipStream_t st, bool* applied);
 int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_t st);
 
 // ---------------------------------------------------------------------------
