@@ -602,24 +602,43 @@ __global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, G
 }
 
 
+// Per-block bounds of the vertices (min and max are exact in fp32; widened
+// to fp64 for the set-up). kVec: xyz 16-byte aligned, read as three float4
+// per 4 vertices.
+template <bool kVec>
 __global__ __launch_bounds__(kBlock) void k_bbox(const float* xyz, int64_t nv, double* part,
                                                  int* bad) {
   __shared__ double s[6][kBlock];
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nv;
-       v += (int64_t)gridDim.x * kBlock) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double x = (double)xyz[3 * v + a];
-      if (!isfinite(x)) *bad = 1;
-      lo[a] = fmin(lo[a], x);
-      hi[a] = fmax(hi[a], x);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool fin = true;
+  auto take = [&](int a, float x) {
+    fin &= isfinite(x);
+    lo[a] = fminf(lo[a], x);
+    hi[a] = fmaxf(hi[a], x);
+  };
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t v_tail = 0;
+  if (kVec) {
+    const float4* g4 = reinterpret_cast<const float4*>(xyz);
+    const int64_t ng = nv / 4;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < ng; g += stride) {
+      const float4 a = g4[3 * g], b = g4[3 * g + 1], c = g4[3 * g + 2];
+      take(0, a.x); take(1, a.y); take(2, a.z);
+      take(0, a.w); take(1, b.x); take(2, b.y);
+      take(0, b.z); take(1, b.w); take(2, c.x);
+      take(0, c.y); take(1, c.z); take(2, c.w);
     }
+    v_tail = 4 * ng;
   }
+  for (int64_t v = v_tail + (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nv; v += stride) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) take(a, xyz[3 * v + a]);
+  }
+  if (!fin) *bad = 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    s[a][threadIdx.x] = lo[a];
-    s[3 + a][threadIdx.x] = hi[a];
+    s[a][threadIdx.x] = (double)lo[a];
+    s[3 + a][threadIdx.x] = (double)hi[a];
   }
   __syncthreads();
   for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -726,8 +745,12 @@ int vox_bbox(const float* xyz, int64_t nv, double lo[3], double hi[3], hipStream
   int rc;
   if ((rc = part.alloc(sizeof(double) * 6 * blocks)) || (rc = bad.alloc(sizeof(int)))) return rc;
   LS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
-  hipLaunchKernelGGL(k_bbox, dim3((unsigned)blocks), dim3(kBlock), 0, st, xyz, nv,
-                     part.as<double>(), bad.as<int>());
+  if ((reinterpret_cast<uintptr_t>(xyz) & 15) == 0)
+    hipLaunchKernelGGL(k_bbox<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, xyz, nv,
+                       part.as<double>(), bad.as<int>());
+  else
+    hipLaunchKernelGGL(k_bbox<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, xyz, nv,
+                       part.as<double>(), bad.as<int>());
   LS_HIP(hipGetLastError());
   std::vector<double> h(6 * blocks);
   int hbad = 0;
@@ -786,8 +809,12 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   SnapArgs* sad = lattice.as<SnapArgs>();
   if (float_in) {
     double* part = reinterpret_cast<double*>(sad + 1);
-    hipLaunchKernelGGL(k_bbox, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv, part,
-                       err.as<int>() + 1);
+    if ((reinterpret_cast<uintptr_t>(xyz) & 15) == 0)
+      hipLaunchKernelGGL(k_bbox<true>, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv,
+                         part, err.as<int>() + 1);
+    else
+      hipLaunchKernelGGL(k_bbox<false>, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv,
+                         part, err.as<int>() + 1);
     hipLaunchKernelGGL(k_lattice, dim3(1), dim3(kBlock), 0, st, part, bb_blocks, nv, ga,
                        err.as<int>() + 1, sad, err.as<int>());
     LS_HIP(hipGetLastError());
