@@ -180,6 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Pyramid P, Cones C, Sched S, 
 // saturation and clamping at the end gives the definition's value.
 constexpr int kColX = 16, kColY = 16, kColZ = 8;
 constexpr int kColThreads = kColX * kColY;
+constexpr int kColTab = kColX > kColY ? kColX : kColY;   // x / y tap entries per axis
 constexpr int kColSlots = 4;             // levels 0..3
 constexpr int kColLdsBytes = 65536;
 constexpr int kColMaxSamples = 8;        // instantiated schedule lengths
@@ -221,11 +222,11 @@ constexpr int col_planes() {
 __host__ __device__ inline int col_planes_rt(int L) { return L == 0 ? 9 : (kColZ >> L) + 2; }
 
 // Table layout (global memory): ZRec[n_cones * kN], then
-// Tap[n_cones * kN][2][16] (x taps by p_x, y taps by p_y).
+// Tap[n_cones * kN][2][kColTab] (x taps by p_x, y taps by p_y).
 inline size_t col_table_bytes(int n_cones, int n_samples) {
-  return (size_t)n_cones * n_samples * (sizeof(ZRec) + 2 * 16 * sizeof(Tap));
+  return (size_t)n_cones * n_samples * (sizeof(ZRec) + 2 * kColTab * sizeof(Tap));
 }
-constexpr size_t kMaxTabBytes = (size_t)kMaxCones * kColMaxSamples * (sizeof(ZRec) + 2 * 16 * sizeof(Tap));
+constexpr size_t kMaxTabBytes = (size_t)kMaxCones * kColMaxSamples * (sizeof(ZRec) + 2 * kColTab * sizeof(Tap));
 
 // Smallest v in [0, g) whose sample coordinate (v + 0.5) + s u is >= 0, and
 // the largest whose coordinate is < g (the coordinate grows with v).
@@ -257,8 +258,8 @@ template <int kN>
 __global__ __launch_bounds__(kColThreads) void k_col_table(Pyramid P, Cones C, Sched S,
                                                            ColLevels CL, ZRec* zt, Tap* xyt) {
   const int n_ck = C.n * kN;
-  for (int e = threadIdx.x; e < n_ck * 32; e += kColThreads) {
-    const int p = e & 15, a = (e >> 4) & 1, ck = e >> 5;
+  for (int e = threadIdx.x; e < n_ck * 2 * kColTab; e += kColThreads) {
+    const int p = e % kColTab, a = (e / kColTab) & 1, ck = e / (2 * kColTab);
     const int c = ck / kN, k = ck % kN;
     const int q = CL.slot[k], lv = S.lv[k];
     const float f = 0.5f + S.s[k] * (float)C.dir[c][a];
@@ -390,14 +391,14 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
   for (int i = 0; i < kColZ; ++i) sum[i] = 0.f;
   float occ[kColZ];
   for (int c = 0; c < C.n; ++c) {
-    const Tap* tc = xyt + 32 * kN * c;
+    const Tap* tc = xyt + 2 * kColTab * kN * c;
     const ZRec* zc = zt + kN * c;
 #pragma unroll
     for (int i = 0; i < kColZ; ++i) occ[i] = 0.f;
 #pragma unroll
     for (int k = 0; k < kN; ++k) {
       const ZRec z = zc[k];
-      const Tap tx = tc[32 * k + px], ty = tc[32 * k + 16 + py];
+      const Tap tx = tc[2 * kColTab * k + px], ty = tc[2 * kColTab * k + kColTab + py];
       const bool in_xy = vx >= z.lo[0] && vx <= z.hi[0] && vy >= z.lo[1] && vy <= z.hi[1];
       const float Dm = in_xy ? S.D[k] : 0.f;
       const int q = CL.slot[k];
