@@ -294,11 +294,17 @@ __global__ __launch_bounds__(kColThreads) void k_col_table(Pyramid P, Cones C, S
 // One (cone, sample) on level L for a thread's column: the planes' bilinear
 // values, then each voxel's z interpolation. Dm is the sample's weight D, or
 // 0 when the column is outside the grid in x or y.
-template <int L>
+// kRowB, kPlaneB > 0: the box strides (bytes) are compile-time constants, so
+// every read of the sample is an immediate offset from one address.
+template <int L, int kRowB = 0, int kPlaneB = 0>
 __device__ inline void col_sample(const char* box, const ZRec& z, int32_t plane_bytes,
                                   int32_t row_bytes, float wx, float wy, float Dm, int32_t vz0,
                                   float occ[kColZ]) {
   constexpr int R = col_planes<L>();
+  if (kRowB > 0) {
+    plane_bytes = kPlaneB;
+    row_bytes = kRowB;
+  }
   float pl[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -341,7 +347,14 @@ __device__ inline void col_sample(const char* box, const ZRec& z, int32_t plane_
 // are traced like the AO cones; its remaining samples SH[kN..) lie on
 // levels >= 3 and are interpolated per column (see below). AO averages the
 // other C.n - 1 cones.
-template <int kN, bool kShadow>
+// kStd: the schedule samples levels 0, 1, 2, 3 (one sample each) with box
+// margin 3 on every level (the 16-cone radius-15 AO of aperture 1), so box
+// k has the compile-time extent kStdBox[k] and sample k the level k.
+constexpr int kStdBox[4][3] = {{22, 22, 14}, {14, 14, 10}, {10, 10, 8}, {8, 8, 7}};
+constexpr int std_row(int q) { return kStdBox[q][0] * 4; }
+constexpr int std_plane(int q) { return kStdBox[q][0] * kStdBox[q][1] * 4; }
+
+template <int kN, bool kShadow, bool kStd>
 __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, Sched S,
                                                            ColLevels CL,
                                                            const ZRec* __restrict__ zt,
@@ -405,11 +418,20 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
       const int32_t row_bytes = CL.sz[q][0] * (int32_t)sizeof(float);
       const int32_t plane_bytes = row_bytes * CL.sz[q][1];
       const char* box = reinterpret_cast<const char*>(lds) + z.c0 + tx.off + ty.off;
-      switch (S.lv[k]) {
-        case 0: col_sample<0>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
-        case 1: col_sample<1>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
-        case 2: col_sample<2>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
-        default: col_sample<3>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+      if (kStd) {
+        switch (k) {   // k is a constant of the unrolled loop
+          case 0: col_sample<0, std_row(0), std_plane(0)>(box, z, 0, 0, tx.w, ty.w, Dm, t0[2], occ); break;
+          case 1: col_sample<1, std_row(1), std_plane(1)>(box, z, 0, 0, tx.w, ty.w, Dm, t0[2], occ); break;
+          case 2: col_sample<2, std_row(2), std_plane(2)>(box, z, 0, 0, tx.w, ty.w, Dm, t0[2], occ); break;
+          default: col_sample<3, std_row(3), std_plane(3)>(box, z, 0, 0, tx.w, ty.w, Dm, t0[2], occ); break;
+        }
+      } else {
+        switch (S.lv[k]) {
+          case 0: col_sample<0>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+          case 1: col_sample<1>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+          case 2: col_sample<2>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+          default: col_sample<3>(box, z, plane_bytes, row_bytes, tx.w, ty.w, Dm, t0[2], occ); break;
+        }
       }
     }
     if (kShadow && c == n_ao) break;   // the shadow cone's occ stays in occ[]
@@ -599,16 +621,32 @@ int launch_cones(ls_lineset* s, const Cones& C, const Sched& S, float* out, hipS
     }
     ZRec* zt = static_cast<ZRec*>(s->cone_tab);
     Tap* xyt = reinterpret_cast<Tap*>(zt + (size_t)C.n * S.n);
+    bool std4 = S.n == 4 && T.n == 4;
+    for (int q = 0; std4 && q < 4; ++q)
+      std4 = S.lv[q] == q && T.lv[q] == q && T.slot[q] == q && T.m[q] == 3 &&
+             T.sz[q][0] == kStdBox[q][0] && T.sz[q][1] == kStdBox[q][1] &&
+             T.sz[q][2] == kStdBox[q][2];
+    if (std4) {
+      hipLaunchKernelGGL(k_col_table<4>, dim3(1), block, 0, st, P, C, S, T, zt, xyt);
+      if (sh_out)
+        hipLaunchKernelGGL((k_cones_col<4, true, true>), grid, block, lds, st, P, C, S, T, zt,
+                           xyt, out, *SH, sh_out);
+      else
+        hipLaunchKernelGGL((k_cones_col<4, false, true>), grid, block, lds, st, P, C, S, T, zt,
+                           xyt, out, S, nullptr);
+      LS_HIP(hipGetLastError());
+      return LS_OK;
+    }
     switch (S.n) {
 #define LS_CONES_CASE(N)                                                                        \
   case N:                                                                                       \
     hipLaunchKernelGGL(k_col_table<N>, dim3(1), block, 0, st, P, C, S, T, zt, xyt);            \
     if (sh_out)                                                                                 \
-      hipLaunchKernelGGL((k_cones_col<N, true>), grid, block, lds, st, P, C, S, T, zt, xyt,    \
-                         out, *SH, sh_out);                                                     \
+      hipLaunchKernelGGL((k_cones_col<N, true, false>), grid, block, lds, st, P, C, S, T, zt,  \
+                         xyt, out, *SH, sh_out);                                                \
     else                                                                                        \
-      hipLaunchKernelGGL((k_cones_col<N, false>), grid, block, lds, st, P, C, S, T, zt, xyt,   \
-                         out, S, nullptr);                                                      \
+      hipLaunchKernelGGL((k_cones_col<N, false, false>), grid, block, lds, st, P, C, S, T, zt, \
+                         xyt, out, S, nullptr);                                                 \
     break;
       LS_CONES_CASE(1) LS_CONES_CASE(2) LS_CONES_CASE(3) LS_CONES_CASE(4)
       LS_CONES_CASE(5) LS_CONES_CASE(6) LS_CONES_CASE(7) LS_CONES_CASE(8)

@@ -118,23 +118,37 @@ def test_lod_pyramid_parity():
     assert s.info().n_levels == len(dims)
 
 
-@pytest.mark.parametrize("grid,aperture", [(40, 1.0), ((37, 20, 29), 1.0), (40, 0.5)])
-def test_illumination_grids_parity(grid, aperture):
-    # cubic and ragged grids (partial 8^3 tiles); aperture 0.5 puts several
-    # samples on one level and gives the shadow cone a schedule whose LDS
-    # boxes exceed the tiled kernel's budget (untiled kernel)
+@pytest.mark.parametrize("grid,aperture,radius,separate",
+                         [(40, 1.0, 15.0, False), ((37, 20, 29), 1.0, 15.0, False),
+                          (40, 0.5, 15.0, False), ((37, 20, 29), 1.0, 6.0, False),
+                          (40, 1.0, 15.0, True)])
+def test_illumination_grids_parity(grid, aperture, radius, separate):
+    # Cubic and ragged grids (partial tiles). Aperture 1, radius 15: the
+    # column kernel specialised for levels 0..3, shadow fused; radius 6: the
+    # generic column kernel (3 samples per cone), shadow fused; aperture 0.5
+    # puts several samples on one level and boxes beyond the LDS budget
+    # (per-voxel kernels). separate: AO and shadow built by two calls (the
+    # column kernel alone, then the per-voxel shadow kernel).
     ls, ref, s = _lod_case(grid=grid, n=800)
     lut = synth.lut_importance_alpha()
     light = synth.LIGHT_DIR
-    L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, ao_cones=16, ao_radius=15.0,
-                        cone_aperture=aperture, build_shadow=True, light_dir=light)
+    if separate:
+        L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, ao_cones=16,
+                            ao_radius=radius, cone_aperture=aperture)
+        L.lineset_build_lod(s, U.dev(lut), opaque=False, cone_aperture=aperture,
+                            build_shadow=True, light_dir=light)
+    else:
+        L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, ao_cones=16,
+                            ao_radius=radius, cone_aperture=aperture, build_shadow=True,
+                            light_dir=light)
     torch.cuda.synchronize()
     _, _, rho, _, _ = O.lod(ref, grid, 32, lut, opaque=False)
-    ao = O.ao_grid(rho, grid, 16, 15.0, aperture)
+    ao = O.ao_grid(rho, grid, 16, radius, aperture)
     sh = O.shadow_grid(rho, grid, np.array(light, dtype=np.float32).astype(np.float64), aperture)
     gao = L.lineset_export(s, L.EXPORT_AO).cpu().numpy()
     gsh = L.lineset_export(s, L.EXPORT_SHADOW).cpu().numpy()
-    print(f"[illum grid={grid} aperture={aperture}] ao max_abs_err={np.abs(gao - ao).max():.3e} "
+    print(f"[illum grid={grid} aperture={aperture} radius={radius} separate={separate}] "
+          f"ao max_abs_err={np.abs(gao - ao).max():.3e} "
           f"sh max_abs_err={np.abs(gsh - sh).max():.3e} ao_min={ao.min():.3f} sh_min={sh.min():.3f}",
           flush=True)
     assert ao.min() < 0.95 and sh.min() < 0.95
