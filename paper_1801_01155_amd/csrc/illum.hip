@@ -370,27 +370,42 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
   const int32_t t0[3] = {kColX * (tile % CL.tiles[0]),
                          kColY * ((tile / CL.tiles[0]) % CL.tiles[1]),
                          kColZ * (tile / (CL.tiles[0] * CL.tiles[1]))};
-  // box copy: a half-wave per row, rows strided over the block's 8 half-waves
-  {
-    const int xl = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+  // box copy: one flat loop over each box's cells (compile-time boxes divide
+  // by constants)
+  if (kStd) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int sx = kStdBox[q][0], sy = kStdBox[q][1], n = sx * sy * kStdBox[q][2];
+      const int32_t dx = P.dims[q][0], dy = P.dims[q][1], dz = P.dims[q][2];
+      const int32_t o0 = (t0[0] >> q) - 3, o1 = (t0[1] >> q) - 3, o2 = (t0[2] >> q) - 3;
+      const float* __restrict__ rho = P.rho + P.off[q];
+      float* box = lds + CL.base[q];
+      for (int i = threadIdx.x; i < n; i += kColThreads) {
+        const int x = i % sx, y = (i / sx) % sy, z = i / (sx * sy);
+        const int32_t gx = min(max(o0 + x, 0), dx - 1), gy = min(max(o1 + y, 0), dy - 1),
+                      gz = min(max(o2 + z, 0), dz - 1);
+        box[i] = rho[((int64_t)gz * dy + gy) * dx + gx];
+      }
+    }
+  } else {
     for (int q = 0; q < CL.n; ++q) {
-      const int lv = CL.lv[q], sx = CL.sz[q][0], sy = CL.sz[q][1], sz = CL.sz[q][2];
+      const int lv = CL.lv[q], sx = CL.sz[q][0], sxy = sx * CL.sz[q][1];
+      const int n = sxy * CL.sz[q][2];
       const int32_t dx = P.dims[lv][0], dy = P.dims[lv][1], dz = P.dims[lv][2];
       const int32_t o0 = (t0[0] >> lv) - CL.m[q], o1 = (t0[1] >> lv) - CL.m[q],
                     o2 = (t0[2] >> lv) - CL.m[q];
       const float* __restrict__ rho = P.rho + P.off[lv];
       float* box = lds + CL.base[q];
-      int y = r0 % sy, zz = r0 / sy;
-      for (int r = r0; r < sy * sz; r += 8) {
-        const int32_t gy = min(max(o1 + y, 0), dy - 1), gz = min(max(o2 + zz, 0), dz - 1);
-        const float* src = rho + ((int64_t)gz * dy + gy) * dx;
-        float* dst = box + r * sx;
-        for (int x = xl; x < sx; x += 32) dst[x] = src[min(max(o0 + x, 0), dx - 1)];
-        y += 8;
-        while (y >= sy) {
-          y -= sy;
-          ++zz;
-        }
+      // cell i = x + sx (y + sy z) of a box below 2^14 cells: (i + 0.5) / s
+      // lies at least 0.5 / s from an integer, far beyond the fp32 error of
+      // (i + 0.5) * (1 / s), so the truncation is the exact quotient
+      const float isx = 1.f / (float)sx, isxy = 1.f / (float)sxy;
+      for (int i = threadIdx.x; i < n; i += kColThreads) {
+        const int z = (int)(((float)i + 0.5f) * isxy), rem = i - z * sxy;
+        const int y = (int)(((float)rem + 0.5f) * isx), x = rem - y * sx;
+        const int32_t gx = min(max(o0 + x, 0), dx - 1), gy = min(max(o1 + y, 0), dy - 1),
+                      gz = min(max(o2 + z, 0), dz - 1);
+        box[i] = rho[((int64_t)gz * dy + gy) * dx + gx];
       }
     }
   }
