@@ -569,13 +569,32 @@ __global__ __launch_bounds__(kBlock) void k_occupancy(const uint32_t* offsets, G
     int32_t bx = (int32_t)(m % mx), by = (int32_t)((m / mx) % my),
             bz = (int32_t)(m / ((int64_t)mx * my));
     unsigned long long bits = 0;
-    for (int k = 0; k < 64; ++k) {
-      const int32_t x = 4 * bx + (k & 3), y = 4 * by + ((k >> 2) & 3), z = 4 * bz + (k >> 4);
-      if (x >= ga.g[0] || y >= ga.g[1] || z >= ga.g[2]) continue;
-      const int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
-      const unsigned n = offsets[v + 1] - offsets[v];
-      if (n > 0) bits |= 1ull << k;
-      mxl = n > mxl ? n : mxl;
+    if ((ga.g[0] & 3) == 0) {
+      // whole macro cells along x: a row of 4 voxels is one aligned 16-byte
+      // load of their offsets plus the next row start
+#pragma unroll 4
+      for (int r = 0; r < 16; ++r) {
+        const int32_t y = 4 * by + (r & 3), z = 4 * bz + (r >> 2);
+        if (y >= ga.g[1] || z >= ga.g[2]) continue;
+        const int64_t v = 4 * (int64_t)bx + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
+        const uint4 a = *reinterpret_cast<const uint4*>(offsets + v);
+        const uint32_t e = offsets[v + 4];
+        const unsigned n[4] = {a.y - a.x, a.z - a.y, a.w - a.z, e - a.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (n[c] > 0) bits |= 1ull << (4 * r + c);
+          mxl = n[c] > mxl ? n[c] : mxl;
+        }
+      }
+    } else {
+      for (int k = 0; k < 64; ++k) {
+        const int32_t x = 4 * bx + (k & 3), y = 4 * by + ((k >> 2) & 3), z = 4 * bz + (k >> 4);
+        if (x >= ga.g[0] || y >= ga.g[1] || z >= ga.g[2]) continue;
+        const int64_t v = x + (int64_t)ga.g[0] * (y + (int64_t)ga.g[1] * z);
+        const unsigned n = offsets[v + 1] - offsets[v];
+        if (n > 0) bits |= 1ull << k;
+        mxl = n > mxl ? n : mxl;
+      }
     }
     occ[m] = bits;
     ne = (unsigned long long)__popcll(bits);
