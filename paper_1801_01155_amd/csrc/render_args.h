@@ -29,6 +29,10 @@ struct RenderArgs {
   // spiral_y) out to ring spiral_r, or rows interleaved over the XCDs when
   // spiral_r < 0
   int32_t spiral_x, spiral_y, spiral_r;
+  // the tiles of the first split_n spiral positions (the innermost rings)
+  // are rendered by split_s workgroups each, on 8 / split_s pixel rows, so
+  // the waves over the densest part of the image hold fewer rays
+  int32_t split_n, split_s;
 };
 
 // Tile queues of the persistent kernel: one contiguous range per XCD.
