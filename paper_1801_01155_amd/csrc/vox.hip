@@ -163,17 +163,25 @@ __global__ __launch_bounds__(kBlock) void k_count(const float* xyz, const int32_
   }
   unsigned long long crossings = 0;
   bool bad = false;
-  for (int64_t s0 = v0; s0 < v1; s0 += 64) {
-    const int64_t v = s0 + lane;
-    if (v < v1) {
-      int32_t q[3];
-      load_vertex<kFloatIn>(xyz, lat, v, sa, q);
-      bad |= !in_range(q, ga);
-      if (v + 1 < v1) {
-        int32_t r[3];
-        load_vertex<kFloatIn>(xyz, lat, v + 1, sa, r);
+  // two 64-vertex chunks per pass, every load issued before any is used;
+  // indices are clamped to the curve's last vertex (v1 > v0 inside the loop)
+  // so the loads need no branch, and clamped lanes add nothing
+  for (int64_t s0 = v0; s0 < v1; s0 += 128) {
+    int32_t q[2][3], r[2][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) crossings += (unsigned long long)abs((r[a] >> 8) - (q[a] >> 8));
+    for (int h = 0; h < 2; ++h) {
+      const int64_t v = s0 + 64 * h + lane;
+      load_vertex<kFloatIn>(xyz, lat, v < v1 ? v : v1 - 1, sa, q[h]);
+      load_vertex<kFloatIn>(xyz, lat, v + 1 < v1 ? v + 1 : v1 - 1, sa, r[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t v = s0 + 64 * h + lane;
+      if (v < v1) bad |= !in_range(q[h], ga);
+      if (v + 1 < v1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          crossings += (unsigned long long)abs((r[h][a] >> 8) - (q[h][a] >> 8));
       }
     }
   }

@@ -104,16 +104,21 @@ def _lod_case(grid=48, n=600):
     return ls, ref, s
 
 
-def test_lod_pyramid_parity():
-    ls, ref, s = _lod_case()
+# 48^3 and (37, 20, 29): every coarse level is small (built through LDS
+# bricks, ragged odd sides); (130, 131, 129): its first coarse level (65 x 66
+# x 65) has more than 2^18 voxels and gets a launch of its own, the rest go
+# through bricks
+@pytest.mark.parametrize("grid", [48, (37, 20, 29), (130, 131, 129)])
+def test_lod_pyramid_parity(grid):
+    ls, ref, s = _lod_case(grid=grid)
     lut = synth.lut_importance_alpha()
     L.lineset_build_lod(s, U.dev(lut), opaque=False)
     torch.cuda.synchronize()
-    cnt, ln, rho, dims, loff = O.lod(ref, 48, 32, lut, opaque=False)
+    cnt, ln, rho, dims, loff = O.lod(ref, grid, 32, lut, opaque=False)
     for what, r in ((L.EXPORT_LOD_COUNT, cnt), (L.EXPORT_LOD_LEN, ln), (L.EXPORT_LOD_RHO, rho)):
         g = L.lineset_export(s, what).cpu().numpy().astype(np.float64)
         err = np.abs(g - r) / np.maximum(np.abs(r), 1e-30)
-        print(f"[lod {what}] max_rel_err={err.max():.3e}", flush=True)
+        print(f"[lod grid={grid} field={what}] max_rel_err={err.max():.3e}", flush=True)
         assert np.allclose(g, r, rtol=1e-5, atol=1e-12)
     assert s.info().n_levels == len(dims)
 
