@@ -950,9 +950,14 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
     if (R.split_s > 1) {
       const int ns = R.split_n * R.split_s;
       if (b < ns) {
+        // groups of kXcds tiles x nsub halves; workgroups are dealt to the
+        // XCDs round-robin, so in a full group the halves of a tile share
+        // an XCD (and its L2) as its lists are read twice
         nsub = R.split_s;
-        sub = b % nsub;
-        b /= nsub;
+        const int grp = b / (kXcds * nsub), r = b - grp * kXcds * nsub;
+        const int w = min(kXcds, R.split_n - grp * kXcds);   // tiles in the group
+        sub = r / w;
+        b = grp * kXcds + r % w;
       } else {
         b -= ns - R.split_n;
       }
