@@ -3,7 +3,9 @@ streamlines x 200 vertices, 256^3 grid, 1920x1080 transparent perspective),
 in the launch configuration bench.py times. The CSR is compared in full;
 the density pyramid and illumination grids on sampled voxels; the frame on
 sampled pixels the oracle renders one by one (including the slowest tiles
-of the frame)."""
+of the frame). At 1920x1080 the launch splits the core tiles over two
+workgroups; the same view at 3840x2160 is beyond the split limit and runs
+unsplit, so both launch forms of the transparent frame are checked."""
 import numpy as np
 import pytest
 import torch
@@ -79,3 +81,22 @@ def test_fullsize_frame_sampled_pixels(scale):
     pix = np.array(pix, dtype=np.int64)
     r, _ = O.render(ref, w["grid"], w["bins"], cam, pixels=pix, lut=lut, **params)
     U.assert_image_parity(img[pix], r, "fullsize 1080p sampled pixels")
+
+
+def test_fullsize_frame_4k_unsplit_sampled_pixels(scale):
+    w, ls, ref, s = scale
+    cam = synth.default_camera((w["grid"],) * 3, 3840, 2160)
+    lut = synth.lut_importance_alpha()
+    params = dict(radius=w["radius"], opaque=False, alpha_stop=0.95, merge_curves=True, shading=1)
+    img = L.lineset_render(s, cam, U.dev(lut), **params)
+    torch.cuda.synchronize()
+    img = img.cpu().numpy().reshape(-1, 4)
+    rng = np.random.default_rng(2)
+    W, H = cam.width, cam.height
+    pix = list(rng.integers(0, W * H, 3000))
+    # the densest part of the view: a 96 x 96 block around the image centre,
+    # where the grid centre projects
+    pix += [(H // 2 - 48 + j) * W + W // 2 - 48 + i for j in range(0, 96, 4) for i in range(0, 96, 4)]
+    pix = np.array(pix, dtype=np.int64)
+    r, _ = O.render(ref, w["grid"], w["bins"], cam, pixels=pix, lut=lut, **params)
+    U.assert_image_parity(img[pix], r, "fullsize 3840x2160 sampled pixels")
