@@ -827,46 +827,56 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   //    scale), read back with the slot count below
   const int64_t nv = s->n_vertices;
   const int bb_blocks = (int)std::min<int64_t>(std::max<int64_t>((nv + kBlock - 1) / kBlock, 1), 1024);
-  DeviceBuf slots(st), err(st), sums64(st), lattice(st);
-  if ((rc = slots.alloc(sizeof(uint64_t) * (C + 1))) || (rc = err.alloc(2 * sizeof(int))) ||
+  // The slot counts [C + 1] (the scan leaves their total at [C]) are
+  // followed in the same buffer by the grid set-up and the error flags, so
+  // one copy reads all three back.
+  struct Header {
+    uint64_t n_slots;
+    SnapArgs sa;
+    int err[2];
+  };
+  static_assert(sizeof(Header) == sizeof(uint64_t) + sizeof(SnapArgs) + 2 * sizeof(int),
+                "header layout");
+  const size_t slot_bytes = sizeof(uint64_t) * (C + 1);
+  DeviceBuf slots(st), sums64(st), lattice(st);
+  if ((rc = slots.alloc(slot_bytes + sizeof(SnapArgs) + 2 * sizeof(int))) ||
       (rc = sums64.alloc(sizeof(uint64_t) * scan_block_sums_len(C))) ||
-      (rc = lattice.alloc(sizeof(SnapArgs) + sizeof(double) * 6 * bb_blocks)))
+      (rc = lattice.alloc(sizeof(double) * 6 * bb_blocks)))
     return rc;
-  LS_HIP(hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
-  SnapArgs* sad = lattice.as<SnapArgs>();
+  SnapArgs* sad = reinterpret_cast<SnapArgs*>(slots.as<char>() + slot_bytes);
+  int* errp = reinterpret_cast<int*>(sad + 1);
+  LS_HIP(hipMemsetAsync(errp, 0, 2 * sizeof(int), st));
   if (float_in) {
-    double* part = reinterpret_cast<double*>(sad + 1);
+    double* part = lattice.as<double>();
     if ((reinterpret_cast<uintptr_t>(xyz) & 15) == 0)
       hipLaunchKernelGGL(k_bbox<true>, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv,
-                         part, err.as<int>() + 1);
+                         part, errp + 1);
     else
       hipLaunchKernelGGL(k_bbox<false>, dim3((unsigned)bb_blocks), dim3(kBlock), 0, st, xyz, nv,
-                         part, err.as<int>() + 1);
+                         part, errp + 1);
     hipLaunchKernelGGL(k_lattice, dim3(1), dim3(kBlock), 0, st, part, bb_blocks, nv, ga,
-                       err.as<int>() + 1, sad, err.as<int>());
+                       errp + 1, sad, errp);
     LS_HIP(hipGetLastError());
   }
   // 1. per-curve slot counts + validation
   if (C > 0) {
     if (float_in)
       hipLaunchKernelGGL((k_count<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), err.as<int>());
+                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), errp);
     else
       hipLaunchKernelGGL((k_count<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), err.as<int>());
+                         curve_off, C, s->n_vertices, sad, ga, slots.as<uint64_t>(), errp);
     LS_HIP(hipGetLastError());
   }
   if ((rc = exclusive_scan_u64(slots.as<uint64_t>(), slots.as<uint64_t>(), C, sums64.as<uint64_t>(),
                                st)))
     return rc;
-  uint64_t n_slots = 0;
-  int herr = 0;
-  SnapArgs hsa{};
-  LS_HIP(hipMemcpyAsync(&n_slots, slots.as<uint64_t>() + C, sizeof(uint64_t),
-                        hipMemcpyDeviceToHost, st));
-  LS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (float_in) LS_HIP(hipMemcpyAsync(&hsa, sad, sizeof(SnapArgs), hipMemcpyDeviceToHost, st));
+  Header hh{};
+  LS_HIP(hipMemcpyAsync(&hh, slots.as<uint64_t>() + C, sizeof(Header), hipMemcpyDeviceToHost, st));
   LS_HIP(hipStreamSynchronize(st));
+  const uint64_t n_slots = hh.n_slots;
+  const int herr = hh.err[0];
+  const SnapArgs hsa = hh.sa;
   if (herr & kErrNonFinite) {
     ls_set_error("non-finite vertex coordinate");
     return LS_EINVAL;
