@@ -34,7 +34,7 @@ typedef enum {
   LS_EINVAL = -1,        /* invalid argument or input data */
   LS_ENOMEM = -2,        /* device or host allocation failed, or a size limit */
   LS_EDEVICE = -3,       /* a HIP runtime call failed */
-  LS_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  LS_EUNSUPPORTED = -4,  /* valid request this library does not implement */
   LS_EBUSY = -5,         /* server cannot queue the request now */
   LS_ETIMEOUT = -6       /* wait ended before completion */
 } ls_status;
