@@ -135,6 +135,7 @@ void ls_free_all(ls_lineset* s) {
   s->offsets = nullptr;
   s->records = nullptr;
   s->occupancy = nullptr;
+  s->stats_pending = false;
   s->lod_count = s->lod_len = s->lod_rho = s->ao = s->sh = nullptr;
   s->cone_tab = nullptr;
   s->cone_tab_bytes = 0;
@@ -408,6 +409,15 @@ int lineset_info(ls_lineset_t s, ls_info* o) {
   if (!s || !o) {
     ls_set_error("lineset_info: null argument");
     return LS_EINVAL;
+  }
+  if (s->stats_pending) {
+    // the voxelizer synchronised its stream: the statistics are final
+    const int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
+    unsigned long long h[2] = {0, 0};
+    LS_HIP(hipMemcpy(h, s->occupancy + nm, sizeof(h), hipMemcpyDeviceToHost));
+    s->nonempty = (int64_t)h[0];
+    s->max_list = (int64_t)(uint32_t)h[1];
+    s->stats_pending = false;
   }
   std::memset(o, 0, sizeof(*o));
   for (int a = 0; a < 3; ++a) o->grid[a] = s->grid[a];

@@ -34,9 +34,11 @@ struct ls_lineset {
   int64_t n_curves, n_vertices;
   int64_t n_records, n_slots;
   int64_t nonempty, max_list;
+  bool stats_pending;  // nonempty and max_list still on the device (after the occupancy words)
   uint32_t* offsets;   // [nvox + 1]
   uint64_t* records;   // [n_records] (at least one element allocated)
-  uint64_t* occupancy; // per 4^3 macro cell: 64-bit mask of its non-empty voxels
+  uint64_t* occupancy; // per 4^3 macro cell: 64-bit mask of its non-empty voxels;
+                       // then the non-empty voxel count (u64) and the longest list (u32)
   int32_t macro[3];    // macro-cell grid dims (ceil(grid / 4))
   // density pyramid
   int32_t n_levels;

@@ -946,21 +946,19 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
     LS_HIP(hipGetLastError());
   }
 
-  // 6. macro-cell occupancy and list statistics
-  DeviceBuf stats(st);
-  if ((rc = stats.alloc(16))) return rc;
-  LS_HIP(hipMemsetAsync(stats.p, 0, 16, st));
+  // 6. macro-cell occupancy and list statistics; the statistics stay on
+  //    the device after the occupancy words until lineset_info asks for them
   for (int a = 0; a < 3; ++a) s->macro[a] = (s->grid[a] + 3) / 4;
   int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
-  if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * nm))) return rc;
+  if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * (nm + 2)))) return rc;
+  char* stats = reinterpret_cast<char*>(s->occupancy + nm);
+  LS_HIP(hipMemsetAsync(stats, 0, 16, st));
   hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nm)), dim3(kBlock), 0, st, s->offsets, ga,
                      s->macro[0], s->macro[1], s->macro[2], (unsigned long long*)s->occupancy,
-                     stats.as<unsigned long long>(), (unsigned int*)(stats.as<char>() + 8));
+                     reinterpret_cast<unsigned long long*>(stats),
+                     reinterpret_cast<unsigned int*>(stats + 8));
   LS_HIP(hipGetLastError());
-  unsigned long long hstats[2] = {0, 0};
-  LS_HIP(hipMemcpyAsync(hstats, stats.p, 16, hipMemcpyDeviceToHost, st));
   LS_HIP(hipStreamSynchronize(st));
-  s->nonempty = (int64_t)hstats[0];
-  s->max_list = (int64_t)(uint32_t)hstats[1];
+  s->stats_pending = true;
   return LS_OK;
 }
