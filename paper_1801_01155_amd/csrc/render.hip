@@ -50,11 +50,16 @@ constexpr int kSortSlots = 4;   // sorted hit buffer of the neighbour mode
 //     960x540 1.63 -> 1.36, but 1920x1080 2.10 -> 2.18.
 // The limit lies between the largest split case (1.1e8 ray-records) and the
 // smallest unsplit one (4.1e8). On the first set any radius of 0.5 to 1.25
-// measured the same, 0.35 and 0.25 worse than no split, as did a 4-way
-// split; on the second, 960x540 took 1.56 ms at 0.5 and 1.36 at 0.75-1.25.
-constexpr int kSplitS = 2;
+// measured the same, 0.35 and 0.25 worse than no split; on the second,
+// 960x540 took 1.56 ms at 0.5 and 1.36 at 0.75-1.25.
+// Frames of at most kSplit4MaxWork split four ways (two rows per
+// workgroup): first set 960x540 0.78 -> 0.66 ms, distant view 0.79 -> 0.61
+// (2.1e7 to 2.8e7 ray-records), while at 1.0e8 and above (first set
+// 1920x1080 1.02 -> 1.21, second set 960x540 1.36 -> 1.48) two ways are
+// better.
 constexpr double kSplitFrac = 1.0;
 constexpr double kSplitMaxWork = 2.0e8;
+constexpr double kSplit4MaxWork = 5.0e7;
 constexpr int kCoopSlots = 4;   // sorted hit buffer of the wave-cooperative own-list mode (8 measured slower)
 constexpr int kMergeSlots = 8;
 constexpr int kXcds = 8;
@@ -1183,11 +1188,11 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
       const double cols = std::cbrt((double)s->grid[0] * s->grid[1] * s->grid[2]);
       const double covered = std::min((double)R.n_tiles, M_PI * r_tiles * r_tiles);
       const double work = 64.0 * covered * (double)s->n_records / (cols * cols);
-      if (wx == 1 && wy == 1 && kSplitS > 1 && !R.opaque && std::isfinite(r_tiles) &&
+      if (wx == 1 && wy == 1 && !R.opaque && std::isfinite(r_tiles) &&
           work <= kSplitMaxWork) {
         const int rs = (int)std::min(kSplitFrac * r_tiles, (double)R.spiral_r);
         R.split_n = (2 * rs + 1) * (2 * rs + 1);
-        R.split_s = kSplitS;
+        R.split_s = work <= kSplit4MaxWork ? 4 : 2;
       }
     }
   }
