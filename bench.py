@@ -60,8 +60,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrivals per rate: max(100, rate * seconds), capped")
     ap.add_argument("--serve-max-requests", type=int, default=2000)
-    ap.add_argument("--serve-inflight-mib", type=float, default=36.0,
-                    help="HBM budget for outputs in flight, beyond the resident sets")
+    ap.add_argument("--serve-arena-mib", type=float, default=36.0,
+                    help="server-owned output arena (HBM budget beyond the resident sets)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="append one 2 GiB device-to-device copy (the reference kernel "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -211,13 +211,15 @@ def _lod_dims(grid):
 
 
 def serve_sweep(L, synth, torch, dev, rates, seconds_per_rate, max_requests,
-                inflight_bytes):
+                arena_bytes):
     """Open-loop serving: Poisson arrivals at each rate over 4 resident sets
     of 1M / 5M / 20M / 50M segments (256^3, 256^3, 512^3, 512^3, AO and
     shadow grids built); resolution uniform over 512^2 / 1280x720 /
-    1920x1080; transparency and AO shading each on with probability 1/2. The
-    HBM budget is the resident sets plus `inflight_bytes` for outputs in
-    flight, so bursts wait for memory."""
+    1920x1080; transparency and AO shading each on with probability 1/2.
+    Requests render into the server's output arena (`arena_bytes`, within
+    the budget); the client collects each finished image while it waits for
+    the next arrival, and a request whose arena block does not fit waits."""
+    from collections import deque
     sets_spec, reqs = synth.serve_workload_spec(n_requests=max_requests)
     lut_tr = torch.as_tensor(synth.lut_importance_alpha()).to(dev)
     lut_op = torch.as_tensor(synth.lut_ramp(1.0)).to(dev)
@@ -236,48 +238,43 @@ def serve_sweep(L, synth, torch, dev, rates, seconds_per_rate, max_requests,
     resident = sum(s.info().device_bytes for s in sets)
     log(f"[bench] serving sets built in {time.perf_counter() - t:.1f}s "
         f"({resident / 2**30:.2f} GiB resident)")
-    ring = 16
-    bufs = {wh: [torch.empty((wh[1], wh[0], 4), dtype=torch.float32, device=dev)
-                 for _ in range(ring)] for wh in synth.SERVE_RESOLUTIONS}
+    dst = {wh: torch.empty((wh[1], wh[0], 4), dtype=torch.float32, device=dev)
+           for wh in synth.SERVE_RESOLUTIONS}
     cams = [synth.look_camera((sets_spec[r["set"]]["grid"],) * 3, r["width"], r["height"],
                               r["direction"], False) for r in reqs]
-    budget = resident + inflight_bytes
+    budget = resident + arena_bytes + (1 << 20)
     rng = np.random.default_rng(55)
     out = {}
     for lam in rates:
         n_req = int(min(max_requests, max(100, lam * seconds_per_rate)))
-        srv = L.Server(budget, n_slots=2, max_batch_views=64)
+        srv = L.Server(budget, n_slots=2, max_batch_views=64, output_arena_bytes=arena_bytes)
         ids = [srv.add_lineset(s) for s in sets]
         arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
-        last = {}
-        use = {wh: 0 for wh in bufs}
-        tickets = []
-        collected = set()
+        pending = deque()
         offered = 0
+
+        def collect(block):
+            while pending and srv.wait(pending[0][0], timeout_us=-1 if block else 0):
+                tk, wh = pending.popleft()
+                srv.result(tk, dst[wh])
+
         t0 = time.perf_counter()
         for k in range(n_req):
             r = reqs[k]
             wh = (r["width"], r["height"])
-            slot = use[wh] % ring
-            use[wh] += 1
-            prev = last.get((wh, slot))
-            if prev is not None and prev not in collected:
-                srv.wait(prev)          # the ring buffer's previous image is done
-                collected.add(prev)
-            while time.perf_counter() - t0 < arrivals[k]:
-                pass
+            while True:
+                collect(False)
+                if time.perf_counter() - t0 >= arrivals[k]:
+                    break
             params = dict(radius=0.4, opaque=not r["transparent"], alpha_stop=0.95,
                           merge_curves=True, shading=2 if r["ao"] else 1,
                           light_dir=synth.LIGHT_DIR)
             tk = srv.submit(ids[r["set"]], cams[k], lut_tr if r["transparent"] else lut_op,
-                            bufs[wh][slot], **params)
-            last[(wh, slot)] = tk
-            tickets.append(tk)
+                            None, **params)
+            pending.append((tk, wh))
             offered += r["width"] * r["height"]
         span = time.perf_counter() - t0
-        for tk in tickets:
-            if tk not in collected:
-                srv.wait(tk)
+        collect(True)
         st = srv.stats()
         out[f"{lam:g}_per_s"] = dict(
             requests=n_req, offered_mrays_s=offered / span / 1e6, p50_ms=st["p50_ms"],
@@ -291,9 +288,9 @@ def serve_sweep(L, synth, torch, dev, rates, seconds_per_rate, max_requests,
     return {
         "workload": "Poisson arrivals over 4 resident sets of 1M/5M/20M/50M segments "
                     "(256^3/256^3/512^3/512^3); 512^2, 1280x720, 1920x1080 uniform; "
-                    "transparency and AO each p=1/2",
+                    "transparency and AO each p=1/2; outputs in a server-owned arena",
         "budget_bytes": int(budget), "resident_bytes": int(resident),
-        "inflight_budget_bytes": int(inflight_bytes), "rates": out,
+        "output_arena_bytes": int(arena_bytes), "rates": out,
     }
 
 
@@ -449,7 +446,7 @@ def main():
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         result["serving"] = serve_sweep(L, synth, torch, dev, rates, args.serve_seconds,
                                         args.serve_max_requests,
-                                        int(args.serve_inflight_mib * 2**20))
+                                        int(args.serve_arena_mib * 2**20))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(ls, w, cam, lut_np, light, args.cpu_sample_rows)

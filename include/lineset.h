@@ -208,11 +208,23 @@ typedef struct {
   int64_t sort_passes;      /* extra passes for voxels with more hits than the sort buffer */
   int64_t merge_evictions;  /* open intervals evicted from the bounded merge table */
   int64_t macro_skips;      /* empty 4^3 macro cells jumped over */
+  int64_t merge_live_evictions; /* evictions of intervals still open at the new hit's entry
+                                   (a later hit of that curve may be blended again) */
+  int64_t merge_overflow_rays;  /* rays with at least one such eviction: an upper bound on
+                                   the pixels that differ from an unbounded table */
 } ls_render_counters;
 
 int lineset_render_counted(ls_lineset_t set, const ls_camera* cam,
                            const ls_render_params* params, float* rgba_out,
                            ls_render_counters* counters, void* hip_stream);
+
+/* The per-curve merge table of a ray holds `merge_slots` open intervals.
+ * When it is full, the interval that closed first is evicted; the image then
+ * equals that of an unbounded table unless an evicted interval is still open
+ * at the new hit and its curve is hit again (merge_live_evictions and
+ * merge_overflow_rays count this). A ray along which at most merge_slots
+ * curves are open at once is exact. */
+int lineset_render_limits(int32_t* merge_slots);
 
 /* ------------------------------------------------------------------------ */
 /* Batched rendering: many views of many resident line sets (uneven sizes,
@@ -263,26 +275,55 @@ int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream
 
 /* ------------------------------------------------------------------------ */
 /* Render server: keeps voxelized line sets resident, admits render requests
- * by an HBM budget and batches them continuously. A scheduler thread owns
- * n_slots launch slots (stream + event + descriptor buffers, allocated at
- * creation; nothing is allocated afterwards). Whenever a slot is free it
- * takes the queue's head requests, in arrival order, while their
- * reservations (W*H*16 bytes of output plus a descriptor) fit into
- * budget - resident sets - requests in flight, and renders them in one
- * batched launch; requests arriving meanwhile go into the next free slot, so
- * batches overlap on the device. Each request's image equals its
+ * by an HBM budget and batches them continuously (section "GPU
+ * implementation": the voxel model stays resident and rendering runs per
+ * view). A scheduler thread owns n_slots launch slots (stream + event +
+ * descriptor buffers). Whenever a slot is free it takes the queue's head
+ * requests, in arrival order, while their memory fits, and renders them in
+ * one batched launch; requests arriving meanwhile go into the next free slot,
+ * so batches overlap on the device. Each request's image equals its
  * lineset_render image.
+ *
+ * Memory. The budget holds the resident sets (their current device bytes,
+ * re-read at every admission, so grids built after ls_server_add_lineset
+ * count), the output arena and the outputs being written:
+ *   - output_arena_bytes > 0: the server allocates that much device memory at
+ *     creation. A request submitted with rgba_out == NULL renders into an
+ *     arena block of W*H*16 bytes (rounded up to 256), taken first-fit when
+ *     the request reaches the head of the queue; while no block fits, the
+ *     head waits (held_for_memory). The block returns to the arena when
+ *     ls_server_result copies the image out. Arena requests must be
+ *     collected, or the queue behind them stalls.
+ *   - rgba_out != NULL: the caller owns the output; the request reserves
+ *     W*H*16 bytes plus a descriptor while in flight, within
+ *     budget - resident sets - arena.
+ * Device memory is allocated only by ls_server_create.
+ *
+ * Ordering. ls_server_submit records an event on hip_stream; the render
+ * waits for it, so work queued on that stream before the call (building the
+ * set's grids, filling the LUT, clearing rgba_out) is done before the render
+ * reads or writes. Completion is observed on the host (ls_server_wait).
+ *
  *   ls_server_add_lineset: the set's device bytes count against the budget
  *     (LS_ENOMEM if they do not fit); the server borrows the set.
  *   ls_server_submit: non-blocking; LS_EBUSY when max_queue requests wait,
- *     LS_ENOMEM when the request alone exceeds what the budget leaves,
- *     LS_EINVAL for invalid views (lineset_render's rules). rgba_out and the
- *     LUT must stay valid until the request completes.
+ *     LS_ENOMEM when the request alone exceeds the arena (rgba_out NULL) or
+ *     what the budget leaves, LS_EINVAL for invalid views (lineset_render's
+ *     rules) or rgba_out NULL without an arena. rgba_out and the LUT must
+ *     stay valid until the request completes.
  *   ls_server_wait: blocks up to timeout_us (negative: forever); LS_OK once
- *     the image is written (the ticket is then retired), LS_ETIMEOUT else.
+ *     the image is written, LS_ETIMEOUT else. A caller-owned request's
+ *     ticket is then retired; an arena request's stays until
+ *     ls_server_result.
+ *   ls_server_result: for a completed arena request, copies the H*W*4 floats
+ *     into dst (device or host memory, dst_bytes large enough) on hip_stream,
+ *     synchronises that stream, returns the block and retires the ticket.
+ *     LS_EBUSY if the request has not completed, LS_EINVAL for other tickets.
  *   ls_server_stats: latency percentiles from submission to observed
  *     completion over all completed requests; Mrays/s over the span from the
- *     first submission to the last completion. */
+ *     first submission to the last completion.
+ *   ls_server_destroy: finishes the work in flight; requests still queued
+ *     behind uncollected arena blocks are dropped. */
 typedef struct ls_server* ls_server_t;
 
 typedef struct {
@@ -290,6 +331,7 @@ typedef struct {
   int32_t n_slots;           /* concurrent batched launches, 1..16 */
   int32_t max_batch_views;   /* requests per launch, 1..4096 */
   int32_t max_queue;         /* waiting requests before LS_EBUSY */
+  size_t output_arena_bytes; /* server-owned output memory (0: none), within the budget */
 } ls_server_config;
 
 typedef struct {
@@ -301,14 +343,18 @@ typedef struct {
   int64_t queued, max_queue_depth, rejected;
   size_t resident_bytes, inflight_bytes;
   int64_t held_for_memory;   /* requests that waited at the queue head because
-                                their reservation did not fit the budget */
+                                their memory did not fit */
+  size_t arena_bytes, arena_in_use;
 } ls_server_report;
 
 int ls_server_create(const ls_server_config* cfg, ls_server_t* out);
 int ls_server_add_lineset(ls_server_t server, ls_lineset_t set, int32_t* set_id);
 int ls_server_submit(ls_server_t server, int32_t set_id, const ls_camera* cam,
-                     const ls_render_params* params, float* rgba_out, uint64_t* ticket);
+                     const ls_render_params* params, float* rgba_out, void* hip_stream,
+                     uint64_t* ticket);
 int ls_server_wait(ls_server_t server, uint64_t ticket, int64_t timeout_us);
+int ls_server_result(ls_server_t server, uint64_t ticket, float* dst, size_t dst_bytes,
+                     int32_t dst_on_device, void* hip_stream);
 int ls_server_stats(ls_server_t server, ls_server_report* out);
 void ls_server_destroy(ls_server_t server);   /* finishes queued work first */
 

@@ -55,7 +55,8 @@ class RenderParams(C.Structure):
 class RenderCounters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("visited", "nonempty", "tested", "hits", "fragments",
                                           "list_bytes", "sort_passes", "merge_evictions",
-                                          "macro_skips")]
+                                          "macro_skips", "merge_live_evictions",
+                                          "merge_overflow_rays")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -256,6 +257,13 @@ def lineset_render_counted(ls: LineSet, cam, lut, out=None, stream=None, **param
     return out, k.as_dict()
 
 
+def lineset_render_limits() -> dict:
+    """Compile-time limits of the ray caster ({'merge_slots'})."""
+    m = C.c_int32()
+    _check(lib().lineset_render_limits(C.byref(m)))
+    return {"merge_slots": m.value}
+
+
 def lineset_info(ls: LineSet) -> Info:
     i = Info()
     _check(lib().lineset_info(ls.handle, C.byref(i)))
@@ -393,7 +401,8 @@ def lineset_render_batch(items, stream=None):
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("n_slots", C.c_int32),
-                ("max_batch_views", C.c_int32), ("max_queue", C.c_int32)]
+                ("max_batch_views", C.c_int32), ("max_queue", C.c_int32),
+                ("output_arena_bytes", C.c_size_t)]
 
 
 class ServerReport(C.Structure):
@@ -401,7 +410,8 @@ class ServerReport(C.Structure):
                 ("max_ms", C.c_double), ("mrays_per_s", C.c_double), ("batches", C.c_int64),
                 ("mean_batch", C.c_double), ("queued", C.c_int64), ("max_queue_depth", C.c_int64),
                 ("rejected", C.c_int64), ("resident_bytes", C.c_size_t),
-                ("inflight_bytes", C.c_size_t), ("held_for_memory", C.c_int64)]
+                ("inflight_bytes", C.c_size_t), ("held_for_memory", C.c_int64),
+                ("arena_bytes", C.c_size_t), ("arena_in_use", C.c_size_t)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -413,8 +423,11 @@ def _bind_server(L):
     L.ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
     L.ls_server_add_lineset.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
     L.ls_server_submit.argtypes = [C.c_void_p, C.c_int32, C.POINTER(CameraS),
-                                   C.POINTER(RenderParams), C.c_void_p, C.POINTER(C.c_uint64)]
+                                   C.POINTER(RenderParams), C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_uint64)]
     L.ls_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64]
+    L.ls_server_result.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t, C.c_int32,
+                                   C.c_void_p]
     L.ls_server_stats.argtypes = [C.c_void_p, C.POINTER(ServerReport)]
     L.ls_server_destroy.argtypes = [C.c_void_p]
     L.ls_server_destroy.restype = None
@@ -425,10 +438,12 @@ class Server:
     """Owns an ls_server_t. Keeps the sets, LUTs and outputs of pending
     requests alive until they are waited for."""
 
-    def __init__(self, hbm_budget_bytes, n_slots=2, max_batch_views=64, max_queue=4096):
+    def __init__(self, hbm_budget_bytes, n_slots=2, max_batch_views=64, max_queue=4096,
+                 output_arena_bytes=0):
         L = lib()
         _bind_server(L)
-        cfg = ServerConfig(hbm_budget_bytes, n_slots, max_batch_views, max_queue)
+        cfg = ServerConfig(hbm_budget_bytes, n_slots, max_batch_views, max_queue,
+                           output_arena_bytes)
         h = C.c_void_p()
         _check(L.ls_server_create(C.byref(cfg), C.byref(h)))
         self.handle = h
@@ -441,21 +456,34 @@ class Server:
         self._sets.append(ls)
         return sid.value
 
-    def submit(self, set_id, cam, lut, out, **params) -> int:
+    def submit(self, set_id, cam, lut, out=None, stream=None, **params) -> int:
+        """Queues a render into `out` (device tensor [H, W, 4]), or into the
+        server's output arena when `out` is None (collect it with result()).
+        Work queued on `stream` (default: the current stream) before the call
+        is done before the render."""
         c = camera_struct(cam)
         p = render_params(lut, **params)
         t = C.c_uint64()
         _check(lib().ls_server_submit(self.handle, set_id, C.byref(c), C.byref(p),
-                                      C.c_void_p(out.data_ptr()), C.byref(t)))
+                                      _ptr(out), _stream(stream), C.byref(t)))
         self._pending[t.value] = (lut, out)
         return t.value
+
+    def result(self, ticket, out, stream=None):
+        """Copies a completed arena request's image into `out` (device tensor
+        [H, W, 4]) and returns its arena block."""
+        _check(lib().ls_server_result(self.handle, C.c_uint64(ticket), _ptr(out),
+                                      out.numel() * out.element_size(), 1, _stream(stream)))
+        self._pending.pop(ticket, None)
+        return out
 
     def wait(self, ticket, timeout_us=-1):
         rc = lib().ls_server_wait(self.handle, C.c_uint64(ticket), C.c_int64(timeout_us))
         if rc == LS_ETIMEOUT:
             return False
         _check(rc)
-        self._pending.pop(ticket, None)
+        if self._pending.get(ticket, (None, None))[1] is not None:
+            self._pending.pop(ticket, None)
         return True
 
     def stats(self):

@@ -7,7 +7,7 @@
 #include <mutex>
 #include <vector>
 
-#include "ls_internal.h"
+#include "render_args.h"
 
 namespace {
 thread_local char g_err[512] = "no error";
@@ -393,15 +393,16 @@ int lineset_render_counted(ls_lineset_t s, const ls_camera* cam, const ls_render
   (void)hipStreamSynchronize(st);
   pool_free(dc);
   if (rc) return rc;
-  counters->visited = (int64_t)h.visited;
-  counters->nonempty = (int64_t)h.nonempty;
-  counters->tested = (int64_t)h.tested;
-  counters->hits = (int64_t)h.hits;
-  counters->fragments = (int64_t)h.fragments;
-  counters->list_bytes = (int64_t)h.list_bytes;
-  counters->sort_passes = (int64_t)h.sort_passes;
-  counters->merge_evictions = (int64_t)h.merge_evictions;
-  counters->macro_skips = (int64_t)h.macro_skips;
+  export_counters(h, counters);
+  return LS_OK;
+}
+
+int lineset_render_limits(int32_t* merge_slots) {
+  if (!merge_slots) {
+    ls_set_error("lineset_render_limits: null argument");
+    return LS_EINVAL;
+  }
+  *merge_slots = render_merge_slots();
   return LS_OK;
 }
 

@@ -264,15 +264,7 @@ int lineset_batch_render_counted(ls_batch_t b, ls_render_counters* c, void* hip_
   RenderCounters h{};
   LS_HIP(hipMemcpyAsync(&h, b->d_queue + 8, sizeof(h), hipMemcpyDeviceToHost, st));
   LS_HIP(hipStreamSynchronize(st));
-  c->visited = (int64_t)h.visited;
-  c->nonempty = (int64_t)h.nonempty;
-  c->tested = (int64_t)h.tested;
-  c->hits = (int64_t)h.hits;
-  c->fragments = (int64_t)h.fragments;
-  c->list_bytes = (int64_t)h.list_bytes;
-  c->sort_passes = (int64_t)h.sort_passes;
-  c->merge_evictions = (int64_t)h.merge_evictions;
-  c->macro_skips = (int64_t)h.macro_skips;
+  export_counters(h, c);
   return LS_OK;
 }
 

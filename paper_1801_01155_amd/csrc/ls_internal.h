@@ -109,8 +109,22 @@ int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_
 // Rendering (render.hip).
 struct RenderCounters {
   unsigned long long visited, nonempty, tested, hits, fragments, list_bytes, sort_passes,
-      merge_evictions, macro_skips;
+      merge_evictions, macro_skips, merge_live_evictions, merge_overflow_rays;
 };
+
+inline void export_counters(const RenderCounters& h, ls_render_counters* c) {
+  c->visited = (int64_t)h.visited;
+  c->nonempty = (int64_t)h.nonempty;
+  c->tested = (int64_t)h.tested;
+  c->hits = (int64_t)h.hits;
+  c->fragments = (int64_t)h.fragments;
+  c->list_bytes = (int64_t)h.list_bytes;
+  c->sort_passes = (int64_t)h.sort_passes;
+  c->merge_evictions = (int64_t)h.merge_evictions;
+  c->macro_skips = (int64_t)h.macro_skips;
+  c->merge_live_evictions = (int64_t)h.merge_live_evictions;
+  c->merge_overflow_rays = (int64_t)h.merge_overflow_rays;
+}
 
 // Validates one view's camera / parameters / output (sets the error text).
 int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params* p,

@@ -61,14 +61,18 @@ constexpr double kSplitFrac = 1.0;
 constexpr double kSplitMaxWork = 2.0e8;
 constexpr double kSplit4MaxWork = 5.0e7;
 constexpr int kCoopSlots = 4;   // sorted hit buffer of the wave-cooperative own-list mode (8 measured slower)
-constexpr int kMergeSlots = 8;
+// Intervals of the per-curve merge table (LDS, 12 bytes each per lane).
+#ifndef LS_MERGE_SLOTS
+#define LS_MERGE_SLOTS 8
+#endif
+constexpr int kMergeSlots = LS_MERGE_SLOTS;
 constexpr int kXcds = 8;
 
 
 
 struct Counts {
   uint32_t visited = 0, nonempty = 0, tested = 0, hits = 0, fragments = 0, passes = 0,
-           evictions = 0, skips = 0;
+           evictions = 0, skips = 0, live_evictions = 0, overflow_rays = 0;
   uint32_t list_bytes = 0;
 };
 
@@ -255,7 +259,13 @@ __device__ inline bool merge_hit(Accum& acc, uint32_t tag, double t_in, double t
       slot = m;
     }
   }
-  if (M.tag[slot * st + l] != 0xFFFFFFFFu) cnt.evictions++;
+  if (M.tag[slot * st + l] != 0xFFFFFFFFu) {
+    // an evicted interval still open at this hit's entry could have merged
+    // a later hit of its curve (with hits in global t order, as in the
+    // neighbour mode, one that closed before t_in never can)
+    cnt.evictions++;
+    if (best >= t_in) cnt.live_evictions++;
+  }
   M.tag[slot * st + l] = tag;
   M.out[slot * st + l] = t_out;
   return false;
@@ -811,10 +821,10 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
 }
 
 __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
-  unsigned long long v[9] = {c.visited, c.nonempty, c.tested, c.hits, c.fragments, c.list_bytes,
-                             c.passes, c.evictions, c.skips};
+  unsigned long long v[11] = {c.visited, c.nonempty, c.tested, c.hits, c.fragments, c.list_bytes,
+                              c.passes, c.evictions, c.skips, c.live_evictions, c.overflow_rays};
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
+  for (int k = 0; k < 11; ++k) {
     unsigned long long x = v[k];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
@@ -830,6 +840,8 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
     atomicAdd(&out->sort_passes, v[6]);
     atomicAdd(&out->merge_evictions, v[7]);
     atomicAdd(&out->macro_skips, v[8]);
+    atomicAdd(&out->merge_live_evictions, v[9]);
+    atomicAdd(&out->merge_overflow_rays, v[10]);
   }
 }
 
@@ -844,6 +856,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
   dda_init(R, ray);
   if (!valid) ray.alive = false;
   Accum acc(mt);
+  const uint32_t live_ev0 = cnt.live_evictions;
   {
     const float dd = dot3(ray.d, ray.d);
     const float inv_dd = 1.f / dd;
@@ -920,6 +933,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
       }
     }
   }
+  if (cnt.live_evictions != live_ev0) cnt.overflow_rays++;
   if (valid) {
     float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
     reinterpret_cast<float4*>(R.out)[(int64_t)j * R.W + i] = px;
@@ -1251,6 +1265,8 @@ int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_sta
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
+
+int render_merge_slots() { return kMergeSlots; }
 
 int batch_blocks_per_cu(int wx, int wy, int* out) {
   int n = 0;

@@ -56,3 +56,4 @@ int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_sta
                         const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
                         bool count, hipStream_t st);
 int batch_blocks_per_cu(int wx, int wy, int* out);
+int render_merge_slots();   // intervals in the per-ray curve-merge table

@@ -7,7 +7,15 @@
 // reservation fits the budget into one batched launch on that slot's stream;
 // requests that arrive while batches run are admitted into the next free
 // slot, so several batches overlap on the device. Completion is observed by
-// polling the slots' events. Nothing is allocated after creation.
+// polling the slots' events.
+//
+// Memory: the budget holds the resident sets, the optional output arena
+// (device memory the server owns, allocated at creation) and the outputs
+// being written by requests in flight. A request submitted without an
+// output buffer renders into a block of the arena, taken first-fit at
+// admission and returned when the caller copies the image out; a request
+// whose block does not fit waits at the head of the queue. Device memory is
+// allocated only at creation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +23,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -32,11 +41,14 @@ struct Request {
   int32_t set_id;
   ls_camera cam;
   ls_render_params params;
-  float* out;
-  size_t bytes;          // reservation against the budget
+  float* out;            // caller's buffer, or the arena block once admitted
+  bool arena = false;    // output in the server's arena
+  size_t bytes;          // caller's buffer: output bytes in flight; arena: block size
+  size_t arena_off = 0;
   Clock::time_point t_submit, t_done;
   int state;             // 0 queued, 1 running, 2 done
   bool held = false;     // was once at the queue head without room in the budget
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
 };
 
 constexpr int kQueueWords = 8 + (int)(sizeof(RenderCounters) / sizeof(unsigned));
@@ -50,7 +62,7 @@ struct Slot {
   RenderArgs* h_args = nullptr;      // pinned
   int32_t* h_tile_start = nullptr;   // pinned
   std::vector<Request*> reqs;
-  size_t bytes = 0;
+  size_t bytes = 0;      // output bytes of the caller-owned requests in the batch
   bool busy = false;
 };
 
@@ -61,7 +73,8 @@ struct ls_server {
   int device = 0;
   BatchPlan plan{2, 2, 0};
   std::vector<ls_lineset_t> sets;
-  size_t resident = 0;
+  size_t resident = 0;      // bytes of the sets at the last admission pass
+  std::vector<hipEvent_t> free_events;  // submission events, reused
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
@@ -69,8 +82,13 @@ struct ls_server {
   std::vector<Slot> slots;
   std::thread sched;
   bool stop = false;
-  size_t inflight = 0;
+  size_t inflight = 0;      // output bytes of caller-owned requests in flight
   uint64_t next_ticket = 1;
+  // output arena: base, size, free blocks (offset -> size, coalesced), bytes in use
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  std::map<size_t, size_t> arena_free;
+  uint64_t arena_returns = 0;   // blocks given back (wakes a scheduler waiting for space)
   // statistics
   std::vector<double> lat_ms;
   uint64_t rays_done = 0, batches = 0, batched_views = 0, rejected = 0, max_depth = 0;
@@ -82,8 +100,54 @@ struct ls_server {
 
 namespace {
 
-size_t reservation(const ls_camera& c) {
-  return (size_t)c.width * (size_t)c.height * 16 + sizeof(RenderArgs);
+constexpr size_t kArenaAlign = 256;
+
+size_t image_bytes(const ls_camera& c) { return (size_t)c.width * (size_t)c.height * 16; }
+
+size_t reservation(const ls_camera& c) { return image_bytes(c) + sizeof(RenderArgs); }
+
+size_t arena_block(const ls_camera& c) {
+  return (image_bytes(c) + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+// First-fit block of `len` bytes from the arena's free list.
+bool arena_take(ls_server* S, size_t len, size_t* off) {
+  for (auto it = S->arena_free.begin(); it != S->arena_free.end(); ++it) {
+    if (it->second < len) continue;
+    *off = it->first;
+    const size_t rest = it->second - len;
+    const size_t at = it->first + len;
+    S->arena_free.erase(it);
+    if (rest) S->arena_free[at] = rest;
+    S->arena_used += len;
+    return true;
+  }
+  return false;
+}
+
+void arena_give(ls_server* S, size_t off, size_t len) {
+  S->arena_used -= len;
+  auto it = S->arena_free.emplace(off, len).first;
+  auto nx = std::next(it);
+  if (nx != S->arena_free.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    S->arena_free.erase(nx);
+  }
+  if (it != S->arena_free.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      S->arena_free.erase(it);
+    }
+  }
+}
+
+// Device bytes of the resident sets now: a set grows when its density
+// pyramid or illumination grids are built after it was added.
+size_t resident_bytes(const ls_server* S) {
+  size_t b = 0;
+  for (const ls_lineset* s : S->sets) b += s->bytes;
+  return b;
 }
 
 // Builds and launches one batch on slot `sl` (caller holds the lock).
@@ -99,6 +163,8 @@ int launch_slot(ls_server* S, Slot& sl) {
   }
   sl.h_tile_start[n] = (int32_t)total;
   const BatchQueues q = make_queues((int)total);
+  // each request's inputs and output were produced on its submitter's stream
+  for (Request* r : sl.reqs) LS_HIP(hipStreamWaitEvent(sl.stream, r->ready, 0));
   LS_HIP(hipMemcpyAsync(sl.d_args, sl.h_args, sizeof(RenderArgs) * n, hipMemcpyHostToDevice,
                         sl.stream));
   LS_HIP(hipMemcpyAsync(sl.d_tile_start, sl.h_tile_start, sizeof(int32_t) * (n + 1),
@@ -128,6 +194,8 @@ void scheduler(ls_server* S) {
       }
       const auto now = Clock::now();
       for (Request* r : sl.reqs) {
+        S->free_events.push_back(r->ready);
+        r->ready = nullptr;
         r->state = 2;
         r->t_done = now;
         S->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
@@ -142,21 +210,33 @@ void scheduler(ls_server* S) {
       S->cv_done.notify_all();
     }
     // admit queued requests into free slots
+    S->resident = resident_bytes(S);
+    bool head_blocked = false;
     for (Slot& sl : S->slots) {
       if (sl.busy || S->queue.empty()) continue;
       while (!S->queue.empty() && (int)sl.reqs.size() < S->cfg.max_batch_views) {
         Request* r = S->queue.front();
-        if (S->resident + S->inflight + sl.bytes + r->bytes > budget) {
+        size_t off = 0;
+        const bool fits =
+            r->arena ? arena_take(S, r->bytes, &off)
+                     : S->resident + S->arena_bytes + S->inflight + sl.bytes + r->bytes <= budget;
+        if (!fits) {
           if (!r->held) {
             r->held = true;
             S->held++;
           }
+          head_blocked = true;
           break;
         }
         S->queue.pop_front();
         r->state = 1;
         sl.reqs.push_back(r);
-        sl.bytes += r->bytes;
+        if (r->arena) {
+          r->arena_off = off;
+          r->out = reinterpret_cast<float*>(S->arena + off);
+        } else {
+          sl.bytes += r->bytes;
+        }
       }
       if (sl.reqs.empty()) break;  // the head does not fit until memory frees
       S->inflight += sl.bytes;
@@ -166,11 +246,16 @@ void scheduler(ls_server* S) {
       S->batched_views += sl.reqs.size();
       if (launch_slot(S, sl) != LS_OK) S->launch_error = LS_EDEVICE;
     }
-    if (S->stop && S->queue.empty() && !any_busy) break;
+    // nothing in flight and the head waits for arena blocks the caller has
+    // not collected: at shutdown it can never run
+    if (S->stop && !any_busy && (S->queue.empty() || head_blocked)) break;
     if (any_busy) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       lk.lock();
+    } else if (head_blocked) {
+      const uint64_t seen = S->arena_returns;
+      S->cv_work.wait(lk, [&] { return S->stop || S->arena_returns != seen; });
     } else {
       S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
     }
@@ -188,9 +273,19 @@ void free_server(ls_server* S) {
     if (sl.h_args) (void)hipHostFree(sl.h_args);
     if (sl.h_tile_start) (void)hipHostFree(sl.h_tile_start);
   }
-  for (auto& kv : S->by_ticket) delete kv.second;
-  for (Request* r : S->queue)
-    if (!S->by_ticket.count(r->ticket)) delete r;
+  if (S->arena) (void)hipFree(S->arena);
+  S->arena = nullptr;
+  for (auto& kv : S->by_ticket) {
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    delete kv.second;
+  }
+  for (Request* r : S->queue) {
+    if (S->by_ticket.count(r->ticket)) continue;
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    delete r;
+  }
+  for (hipEvent_t e : S->free_events) (void)hipEventDestroy(e);
+  S->free_events.clear();
 }
 
 }  // namespace
@@ -204,9 +299,10 @@ int ls_server_create(const ls_server_config* cfg, ls_server_t* out) {
   }
   *out = nullptr;
   if (cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->max_batch_views < 1 ||
-      cfg->max_batch_views > 4096 || cfg->max_queue < 1 || cfg->hbm_budget_bytes == 0) {
+      cfg->max_batch_views > 4096 || cfg->max_queue < 1 || cfg->hbm_budget_bytes == 0 ||
+      cfg->output_arena_bytes > cfg->hbm_budget_bytes) {
     ls_set_error("ls_server_create: need 1..16 slots, 1..4096 views per batch, max_queue >= 1, "
-                 "a non-zero budget");
+                 "a non-zero budget holding the output arena");
     return LS_EINVAL;
   }
   ls_server* S = new (std::nothrow) ls_server();
@@ -243,6 +339,19 @@ int ls_server_create(const ls_server_config* cfg, ls_server_t* out) {
       return LS_ENOMEM;
     }
   }
+  if (cfg->output_arena_bytes > 0) {
+    S->arena_bytes = cfg->output_arena_bytes / kArenaAlign * kArenaAlign;
+    if (S->arena_bytes == 0 || hipMalloc(&S->arena, S->arena_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      S->arena = nullptr;
+      free_server(S);
+      delete S;
+      ls_set_error("ls_server_create: output arena of %zu bytes not allocated",
+                   (size_t)cfg->output_arena_bytes);
+      return LS_ENOMEM;
+    }
+    S->arena_free[0] = S->arena_bytes;
+  }
   S->sched = std::thread(scheduler, S);
   *out = S;
   return LS_OK;
@@ -254,7 +363,8 @@ int ls_server_add_lineset(ls_server_t S, ls_lineset_t set, int32_t* set_id) {
     return LS_EINVAL;
   }
   std::lock_guard<std::mutex> lk(S->mu);
-  if (S->resident + set->bytes > S->cfg.hbm_budget_bytes) {
+  S->resident = resident_bytes(S);
+  if (S->resident + S->arena_bytes + set->bytes > S->cfg.hbm_budget_bytes) {
     ls_set_error("ls_server_add_lineset: resident sets would exceed the HBM budget");
     return LS_ENOMEM;
   }
@@ -265,7 +375,8 @@ int ls_server_add_lineset(ls_server_t S, ls_lineset_t set, int32_t* set_id) {
 }
 
 int ls_server_submit(ls_server_t S, int32_t set_id, const ls_camera* cam,
-                     const ls_render_params* params, float* rgba_out, uint64_t* ticket) {
+                     const ls_render_params* params, float* rgba_out, void* hip_stream,
+                     uint64_t* ticket) {
   if (!S || !cam || !params || !ticket) {
     ls_set_error("ls_server_submit: null argument");
     return LS_EINVAL;
@@ -277,10 +388,21 @@ int ls_server_submit(ls_server_t S, int32_t set_id, const ls_camera* cam,
       ls_set_error("ls_server_submit: unknown set id %d", set_id);
       return LS_EINVAL;
     }
-    if ((rc = check_render(S->sets[set_id], cam, params, rgba_out))) return rc;
-    const size_t bytes = reservation(*cam);
-    if (S->resident + bytes > S->cfg.hbm_budget_bytes) {
-      ls_set_error("ls_server_submit: request needs %zu bytes, more than the budget leaves", bytes);
+    const bool in_arena = rgba_out == nullptr;
+    if (in_arena && !S->arena) {
+      ls_set_error("ls_server_submit: rgba_out is NULL and the server has no output arena");
+      return LS_EINVAL;
+    }
+    // an arena request is validated against the (aligned) arena base
+    if ((rc = check_render(S->sets[set_id], cam, params,
+                           in_arena ? reinterpret_cast<const float*>(S->arena) : rgba_out)))
+      return rc;
+    const size_t bytes = in_arena ? arena_block(*cam) : reservation(*cam);
+    S->resident = resident_bytes(S);
+    if (in_arena ? bytes > S->arena_bytes
+                 : S->resident + S->arena_bytes + bytes > S->cfg.hbm_budget_bytes) {
+      ls_set_error("ls_server_submit: request needs %zu bytes, more than the %s can hold", bytes,
+                   in_arena ? "output arena" : "budget");
       return LS_ENOMEM;
     }
     if ((int)S->queue.size() >= S->cfg.max_queue) {
@@ -293,11 +415,28 @@ int ls_server_submit(ls_server_t S, int32_t set_id, const ls_camera* cam,
       ls_set_error("host allocation failed");
       return LS_ENOMEM;
     }
+    if (!S->free_events.empty()) {
+      r->ready = S->free_events.back();
+      S->free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      delete r;
+      ls_set_error("ls_server_submit: event creation failed");
+      return LS_EDEVICE;
+    }
+    if (hipEventRecord(r->ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+      (void)hipGetLastError();
+      S->free_events.push_back(r->ready);
+      delete r;
+      ls_set_error("ls_server_submit: recording on the caller's stream failed");
+      return LS_EDEVICE;
+    }
     r->ticket = S->next_ticket++;
     r->set_id = set_id;
     r->cam = *cam;
     r->params = *params;
     r->out = rgba_out;
+    r->arena = in_arena;
     r->bytes = bytes;
     r->state = 0;
     r->t_submit = Clock::now();
@@ -333,11 +472,61 @@ int ls_server_wait(ls_server_t S, uint64_t ticket, int64_t timeout_us) {
     ls_set_error("ls_server_wait: timed out");
     return LS_ETIMEOUT;
   }
-  S->by_ticket.erase(it);
-  delete r;
+  if (!r->arena) {
+    // an arena request stays until ls_server_result copies its image out
+    S->by_ticket.erase(it);
+    delete r;
+  }
   if (S->launch_error) {
     ls_set_error("ls_server_wait: a batched launch failed");
     return S->launch_error;
+  }
+  return LS_OK;
+}
+
+int ls_server_result(ls_server_t S, uint64_t ticket, float* dst, size_t dst_bytes,
+                     int32_t dst_on_device, void* hip_stream) {
+  if (!S || !dst) {
+    ls_set_error("ls_server_result: null argument");
+    return LS_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->by_ticket.find(ticket);
+    if (it == S->by_ticket.end() || !it->second->arena) {
+      ls_set_error("ls_server_result: unknown ticket, already collected, or not an arena request");
+      return LS_EINVAL;
+    }
+    r = it->second;
+    if (r->state != 2) {
+      ls_set_error("ls_server_result: request not complete (ls_server_wait first)");
+      return LS_EBUSY;
+    }
+    if (dst_bytes < image_bytes(r->cam)) {
+      ls_set_error("ls_server_result: destination holds %zu bytes, %zu needed", dst_bytes,
+                   image_bytes(r->cam));
+      return LS_EINVAL;
+    }
+  }
+  // the block is still held: no other request writes it until it is returned
+  const hipError_t e1 = hipMemcpyAsync(dst, r->out, image_bytes(r->cam),
+                                       dst_on_device ? hipMemcpyDeviceToDevice
+                                                     : hipMemcpyDeviceToHost, st);
+  const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(st) : e1;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    arena_give(S, r->arena_off, r->bytes);
+    S->arena_returns++;
+    S->by_ticket.erase(ticket);
+    delete r;
+  }
+  S->cv_work.notify_one();   // a request held for arena space may fit now
+  if (e2 != hipSuccess) {
+    (void)hipGetLastError();
+    ls_set_error("ls_server_result: copy failed: %s", hipGetErrorString(e2));
+    return LS_EDEVICE;
   }
   return LS_OK;
 }
@@ -371,6 +560,8 @@ int ls_server_stats(ls_server_t S, ls_server_report* o) {
   o->held_for_memory = (int64_t)S->held;
   o->resident_bytes = S->resident;
   o->inflight_bytes = S->inflight;
+  o->arena_bytes = S->arena_bytes;
+  o->arena_in_use = S->arena_used;
   return LS_OK;
 }
 

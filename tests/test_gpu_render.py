@@ -145,3 +145,56 @@ def test_deterministic_frames(medium):
     a = L.lineset_render(s, cam, lut, radius=0.4)
     b = L.lineset_render(s, cam, lut, radius=0.4)
     assert torch.equal(a, b)
+
+
+# --- bounded merge table -----------------------------------------------------------------
+def _bundle_along_z(n, grid=16):
+    """n straight lines along z (the view direction below) through a bundle of
+    bin-centre positions within 2/32 voxel of (8.5, 8.5): a ray down the
+    bundle stays inside every tube, so every curve's interval stays open over
+    the whole bundle (its capsules overlap at the joints)."""
+    offs = sorted(((i, j) for i in range(-2, 3) for j in range(-2, 3)),
+                  key=lambda p: (p[0] ** 2 + p[1] ** 2, p))
+    lat, off = [], [0]
+    for (i, j) in offs[:n]:
+        x = 8 * 256 + 128 + 4 + 8 * i
+        y = 8 * 256 + 128 + 4 + 8 * j
+        lat += [[x, y, 307], [x, y, 256 * (grid - 1) - 20]]
+        off.append(len(lat))
+    lat = np.array(lat, np.int32)
+    return lat, np.array(off, np.int64)
+
+
+@pytest.mark.parametrize("extra", [0, 4])
+def test_merge_table_deep_bundle(extra):
+    """A bundle seen end-on, alpha 0.05 per curve, no termination. With at most
+    as many curves as the merge table holds, the image equals the oracle's
+    (unbounded table) and no open interval is evicted. With more, evictions
+    of open intervals re-blend curves; every pixel that differs from the
+    oracle is counted in merge_overflow_rays."""
+    K = L.lineset_render_limits()["merge_slots"]
+    n = K + extra
+    grid = 16
+    lat, off = _bundle_along_z(n, grid)
+    ref = O.voxelize(lat, off, None, (grid,) * 3, 32)
+    s = L.lineset_voxelize(off, grid, 32, lattice=lat)
+    lut = synth.lut_constant((0.3, 0.7, 0.9), 0.05)
+    cam = synth.Camera((8.5 + 1 / 64, 8.5 + 1 / 64, 24.0), (0.0, 0.0, -1.0), (0.6, 0.0, 0.0),
+                       (0.0, 0.6, 0.0), 16, 16, True)
+    for mode in (0, 1):
+        kw = dict(radius=0.4, opaque=False, alpha_stop=1.01, merge_curves=True, shading=0,
+                  mode=mode)
+        g, k = L.lineset_render_counted(s, cam, U.dev(lut), **kw)
+        torch.cuda.synchronize()
+        r, _ = O.render(ref, grid, 32, cam, lut=lut, **kw)
+        g = g.cpu().numpy()
+        err = np.abs(g.astype(np.float64) - r).max(-1)
+        bad = int((err > U.IMAGE_TOL).sum())
+        print(f"[merge bundle n={n} K={K} mode={mode}] differing={bad} counters={k} "
+              f"centre A gpu={g[8, 8, 3]:.4f} oracle={r[8, 8, 3]:.4f}", flush=True)
+        assert bad <= k["merge_overflow_rays"]
+        if extra == 0:
+            assert k["merge_live_evictions"] == 0 and bad == 0
+            assert abs(r[8, 8, 3] - (1 - 0.95 ** n)) < 1e-6
+        else:
+            assert k["merge_overflow_rays"] > 0
