@@ -53,6 +53,8 @@ def parse():
                     help="skip the batched / served comparison")
     ap.add_argument("--cpu-sample-rows", type=int, default=8,
                     help="oracle renders every k-th image row")
+    ap.add_argument("--no-update", action="store_true",
+                    help="skip the incremental-update leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the open-loop serving sweep")
     ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
@@ -198,6 +200,54 @@ def batched_vs_plain(L, synth, torch, dev, stream, reps):
         "autotune_s": tune_s,
         "served": served,
     }
+
+
+def update_leg(L, synth, torch, dev, stream, ls, w, reps=5, frac=0.01):
+    """Incremental update vs full re-voxelization on the scale workload: each
+    update removes `frac` of the curves (random ids) and appends as many new
+    curves (another seed of the same flow, clamped into the set's box)."""
+    grid, bins = w["grid"], w["bins"]
+    xyz = torch.as_tensor(ls.xyz).to(dev)
+    off = torch.as_tensor(ls.curve_off).to(dev)
+    attr = torch.as_tensor(ls.attr).to(dev)
+    k = max(1, int(frac * ls.n_curves))
+    new = synth.abc_lineset(k, w["n_vertices"], 77, w["perturb"])
+    lo, hi = ls.xyz.min(0), ls.xyz.max(0)
+    nxyz = torch.as_tensor(np.clip(new.xyz, lo, hi).astype(np.float32)).to(dev)
+    noff = torch.as_tensor(new.curve_off).to(dev)
+    nattr = torch.as_tensor(new.attr).to(dev)
+    rng = np.random.default_rng(8)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        s = L.lineset_voxelize(off, grid, bins, xyz=xyz, attr=attr, stream=stream)
+    stream.synchronize()
+    full, upd = [], []
+    n_curves = ls.n_curves
+    for r in range(reps + 1):
+        rm = torch.as_tensor(rng.choice(n_curves, k, replace=False).astype(np.int64)).to(dev)
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            L.lineset_update(s, remove=rm, curve_off=noff, xyz=nxyz, attr=nattr, stream=stream)
+            e1.record(stream)
+            e2.record(stream)
+            t = L.lineset_voxelize(off, grid, bins, xyz=xyz, attr=attr, stream=stream)
+            e3.record(stream)
+        stream.synchronize()
+        t.close()
+        n_curves += k
+        if r > 0:
+            upd.append(e0.elapsed_time(e1))
+            full.append(e2.elapsed_time(e3))
+    info = s.info()
+    s.close()
+    res = {"workload": f"scale set; per update remove {k} curves and add {k} "
+                       f"({frac:.0%} of {ls.n_curves})",
+           "update_ms_median": float(np.median(upd)), "full_voxelize_ms_median":
+           float(np.median(full)), "records_after": int(info.n_records),
+           "curves_after": int(info.n_curves)}
+    log(f"[bench] update: {res}")
+    return res
 
 
 def _lod_dims(grid):
@@ -440,6 +490,8 @@ def main():
         "counters": cnt,
     }
     s.close()
+    if not args.no_update:
+        result["update"] = update_leg(L, synth, torch, dev, stream, ls, w)
     if not args.no_batch:
         result["batched"] = batched_vs_plain(L, synth, torch, dev, stream, max(3, args.steps // 2))
     if not args.no_serve:

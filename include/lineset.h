@@ -112,6 +112,38 @@ typedef struct {
 
 int lineset_voxelize(const ls_voxelize_desc* desc, void* hip_stream, ls_lineset_t* out);
 
+/* Incremental update (section "Voxel-based curve discretization", first
+ * paragraph: on the GPU the pre-process permits instant updates when curves
+ * are removed or added; section "Conclusion and future work": local updates
+ * and time-varying line sets). Removes the curves listed in remove_ids (ids
+ * of the set, duplicates allowed) and appends the given curves, without
+ * re-voxelizing the curves that stay. The set then holds exactly what
+ * lineset_voxelize returns for the edited curve list in lattice form: old
+ * curves keep their ids and removed ones contribute nothing, added curves
+ * take ids n_curves, n_curves + 1, ... (lineset_info's n_curves grows by
+ * the added count). Added vertices are given like lineset_voxelize's: `xyz`
+ * is mapped with the set's own grid set-up (the set must come from xyz
+ * input), `lattice` is used as given; either must lie in [0, 256 * grid).
+ * The density pyramid and illumination grids are released (they describe
+ * the old lines): call lineset_build_lod again.
+ * Errors: LS_EINVAL for a removed id outside [0, n_curves), a vertex outside
+ * the grid, malformed curve_off; LS_EUNSUPPORTED when the set would hold more
+ * than 2^24 curves (the records' curve tags would repeat); LS_ENOMEM. On an
+ * error the set is unchanged. Synchronises the stream. */
+typedef struct {
+  const float* xyz;          /* added curves: [n_vertices][3] world coordinates, or NULL */
+  const int32_t* lattice;    /* [n_vertices][3] lattice coordinates, or NULL */
+  const int64_t* curve_off;  /* [n_curves + 1] */
+  const uint8_t* curve_attr; /* [n_curves], or NULL for 255 */
+  int64_t n_vertices;
+  int64_t n_curves;
+  const int64_t* remove_ids; /* [n_remove] curve ids to remove */
+  int64_t n_remove;
+  int32_t on_device;         /* 1: the pointers are device memory; 0: host */
+} ls_update_desc;
+
+int lineset_update(ls_lineset_t set, const ls_update_desc* desc, void* hip_stream);
+
 void lineset_destroy(ls_lineset_t set);
 
 /* ------------------------------------------------------------------------ */
@@ -171,7 +203,11 @@ int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_strea
  *   shading 2: rgb (ka AO(x) + kd SH(x) max(0, n.L)) + ks SH(x) max(0, n.h)^shininess
  * (v towards the eye, h = normalize(L + v), AO/SH trilinear at the entry).
  * Premultiplied front-to-back: C += (1 - A) a c, A += (1 - A) a; the ray stops
- * once A >= alpha_stop (opaque lines: a = 1).
+ * once A >= alpha_stop (opaque lines: a = 1). Opacity a = lut alpha, or with
+ * distance_alpha (section "Transparency rendering": opacity dependent on the
+ * distance the ray travels inside the tube) a = 1 - (1 - lut alpha)^(l / 2r),
+ * l = |d| (t_out - t_in) the chord of the composited hit (a merged hit adds
+ * nothing; a tangent hit, l = 0, is transparent).
  *   lut_rgba   device, float [256][4] straight alpha
  *   rgba_out   device, float [height][width][4], premultiplied (C, A)
  * Errors: LS_EINVAL for a zero or negative size, radius <= 0 (or >= 1 in
@@ -191,6 +227,7 @@ typedef struct {
   int32_t shading;
   float ka, kd, ks, shininess;
   float light_dir[3];
+  int32_t distance_alpha;    /* 1: opacity from the chord length (see below) */
 } ls_render_params;
 
 int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,

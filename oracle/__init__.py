@@ -51,7 +51,8 @@ class ParamsS(C.Structure):
                 ("alpha_stop", C.c_float), ("merge_curves", C.c_int32),
                 ("lut_rgba", C.POINTER(C.c_float)), ("shading", C.c_int32),
                 ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
-                ("shininess", C.c_float), ("light_dir", C.c_float * 3)]
+                ("shininess", C.c_float), ("light_dir", C.c_float * 3),
+                ("distance_alpha", C.c_int32)]
 
 
 class CountersS(C.Structure):
@@ -262,7 +263,7 @@ def decode(rec: int, bins: int):
 
 def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   lut=None, shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
-                  light_dir=(0.0, 0.0, 1.0)):
+                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False):
     p = ParamsS()
     p.radius = radius
     p.mode = mode
@@ -274,6 +275,7 @@ def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curve
     p.shading = shading
     p.ka, p.kd, p.ks, p.shininess = ka, kd, ks, shininess
     p.light_dir[:] = [float(x) for x in light_dir]
+    p.distance_alpha = int(distance_alpha)
     return p, lut  # keep lut alive
 
 

@@ -790,6 +790,15 @@ static void render_pixel(const rctx* c, int32_t i, int32_t j, double out[4], or_
       const float* lut = p->lut_rgba + 4 * attr;
       double base[3] = {lut[0], lut[1], lut[2]};
       double alpha = p->opaque ? 1.0 : (double)lut[3];
+      if (!p->opaque && p->distance_alpha) {
+        /* Section "Transparency rendering": opacity dependent on the distance
+         * travelled inside the tube. Reading: the transfer function's alpha
+         * is that of a chord of one diameter (2r); a chord of length l has
+         * 1 - (1 - alpha)^(l / 2r), the Beer-Lambert law for a uniform
+         * medium. l is the chord of this (composited) hit. */
+        double chord = (H->t_out - H->t_in) * dl;
+        alpha = 1.0 - pow(1.0 - alpha, chord / (2.0 * (double)p->radius));
+      }
       double col[3];
       if (p->shading == 0) {
         for (int q = 0; q < 3; ++q) col[q] = base[q];

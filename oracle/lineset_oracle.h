@@ -86,6 +86,7 @@ typedef struct {
   int32_t shading;       /* 0 flat colour, 1 head-light Phong, 2 AO + shadow */
   float ka, kd, ks, shininess;
   float light_dir[3];    /* towards the light, unit length */
+  int32_t distance_alpha; /* 1: opacity from the chord length inside the tube */
 } or_params;
 
 typedef struct {

@@ -49,7 +49,8 @@ class RenderParams(C.Structure):
     _fields_ = [("radius", C.c_float), ("mode", C.c_int32), ("opaque", C.c_int32),
                 ("alpha_stop", C.c_float), ("merge_curves", C.c_int32), ("lut_rgba", C.c_void_p),
                 ("shading", C.c_int32), ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
-                ("shininess", C.c_float), ("light_dir", C.c_float * 3)]
+                ("shininess", C.c_float), ("light_dir", C.c_float * 3),
+                ("distance_alpha", C.c_int32)]
 
 
 class RenderCounters(C.Structure):
@@ -190,6 +191,43 @@ def lineset_voxelize(curve_off, grid, bins=32, xyz=None, lattice=None, attr=None
     return LineSet(h.value)
 
 
+class UpdateDesc(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("lattice", C.c_void_p), ("curve_off", C.c_void_p),
+                ("curve_attr", C.c_void_p), ("n_vertices", C.c_int64), ("n_curves", C.c_int64),
+                ("remove_ids", C.c_void_p), ("n_remove", C.c_int64), ("on_device", C.c_int32)]
+
+
+def lineset_update(ls: LineSet, remove=None, curve_off=None, xyz=None, lattice=None, attr=None,
+                   stream=None) -> None:
+    """Removes curves by id and appends curves (device tensors or arrays)."""
+    d = UpdateDesc()
+    keep = []
+    if remove is not None:
+        rm = _dev(remove, torch.int64)
+        keep.append(rm)
+        d.remove_ids = rm.data_ptr() if rm.numel() else None
+        d.n_remove = rm.numel()
+    if curve_off is not None:
+        off = _dev(curve_off, torch.int64)
+        keep.append(off)
+        d.curve_off = off.data_ptr()
+        d.n_curves = off.shape[0] - 1
+        for name, arr, dt in (("xyz", xyz, torch.float32), ("lattice", lattice, torch.int32)):
+            if arr is not None:
+                t = _dev(arr, dt)
+                keep.append(t)
+                setattr(d, name, t.data_ptr() if t.numel() else None)
+                d.n_vertices = t.shape[0]
+        if attr is not None:
+            a = _dev(attr, torch.uint8)
+            keep.append(a)
+            d.curve_attr = a.data_ptr() if a.numel() else None
+    d.on_device = 1
+    L = lib()
+    L.lineset_update.argtypes = [C.c_void_p, C.POINTER(UpdateDesc), C.c_void_p]
+    _check(L.lineset_update(ls.handle, C.byref(d), _stream(stream)))
+
+
 def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=16,
                       ao_radius=15.0, cone_aperture=1.0, build_shadow=False,
                       light_dir=(0.0, 0.0, 1.0), stream=None):
@@ -220,7 +258,7 @@ def camera_struct(cam) -> CameraS:
 
 def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
-                  light_dir=(0.0, 0.0, 1.0)) -> RenderParams:
+                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False) -> RenderParams:
     p = RenderParams()
     p.radius = radius
     p.mode = mode
@@ -231,6 +269,7 @@ def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_
     p.shading = shading
     p.ka, p.kd, p.ks, p.shininess = ka, kd, ks, shininess
     p.light_dir = (C.c_float * 3)(*light_dir)
+    p.distance_alpha = int(distance_alpha)
     return p
 
 

@@ -32,6 +32,7 @@ struct ls_lineset {
   int32_t bins;
   int64_t nvox;
   int64_t n_curves, n_vertices;
+  int64_t curve_base;  // id of the first curve voxelized by vox_build (curve tag offset)
   int64_t n_records, n_slots;
   int64_t nonempty, max_list;
   bool stats_pending;  // nonempty and max_list still on the device (after the occupancy words)
@@ -92,6 +93,8 @@ int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_
 // device and s->lo_scale is set; lattice input (lat): used as given.
 int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
               const uint8_t* attr, hipStream_t st);
+// Occupancy words and list statistics of s->offsets (allocates s->occupancy).
+int vox_occupancy(ls_lineset* s, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Density pyramid and illumination (lod.hip, illum.hip).

@@ -274,17 +274,32 @@ __device__ inline bool merge_hit(Accum& acc, uint32_t tag, double t_in, double t
 struct Shade {
   float v[3];   // towards the eye, unit
   float h[3];   // half vector for the directional light
+  float dlen;   // |d|: ray parameter -> distance
 };
 
+// Opacity of a fragment. Constant per line, or (distance_alpha) dependent on
+// the distance the ray travels inside the tube (section "Transparency
+// rendering"): the LUT opacity a holds for a chord of one tube diameter, so a
+// chord of length l has opacity 1 - (1 - a)^(l / 2r) (a tangent hit, l = 0,
+// has none).
+__device__ inline float fragment_alpha(const RenderArgs& R, float a, float chord) {
+  if (R.opaque) return 1.f;
+  if (!R.dist_alpha) return a;
+  if (!(chord > 0.f)) return 0.f;
+  if (a >= 1.f) return 1.f;
+  return 1.f - __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.f - a) * (chord * R.inv_2r));
+}
+
 // Shade and composite one fragment. p is the entry point in the frame of
-// `cell`, a/b the record's endpoints in the same frame.
+// `cell`, a/b the record's endpoints in the same frame, dt the ray-parameter
+// length of the hit (exit - entry).
 __device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const float4* lut_lds, const Shade& S, Accum& acc, uint64_t rec,
                                  const int32_t cell[3], const float p[3], const float a[3],
-                                 const float b[3], Counts& cnt) {
+                                 const float b[3], float dt, Counts& cnt) {
   #pragma clang fp contract(fast)
   const int attr = (int)((rec >> 32) & 0xFF);
   const float4 lut = lut_lds[attr];
-  const float alpha = R.opaque ? 1.f : lut.w;
+  const float alpha = fragment_alpha(R, lut.w, dt * S.dlen);
   float col[3] = {lut.x, lut.y, lut.z};
   if (R.shading != 0) {
     float ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
@@ -660,7 +675,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
-        composite(R, lut_lds, S, acc, rec, vcell, p, a, b, cnt);
+        composite(R, lut_lds, S, acc, rec, vcell, p, a, b, 0.f, cnt);
         acc.done = true;
       }
     }
@@ -734,7 +749,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rc >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
-        composite(R, lut_lds, S, acc, rc, vcell, p, a, b, cnt);
+        composite(R, lut_lds, S, acc, rc, vcell, p, a, b, t_out - t_in, cnt);
       }
       need = more && !acc.done;
       if (need) cnt.passes++;
@@ -811,7 +826,7 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + s_in * ray.d[c];
-      composite(R, lut_lds, S, acc, rec, w, p, a, b, cnt);
+      composite(R, lut_lds, S, acc, rec, w, p, a, b, len, cnt);
       if (R.opaque) acc.done = true;
     }
     if (acc.done || !more) break;
@@ -873,6 +888,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
     S.h[0] = h[0] * ih;
     S.h[1] = h[1] * ih;
     S.h[2] = h[2] * ih;
+    S.dlen = __builtin_sqrtf(dd);
     // every step moves one cell monotonically along one axis: at most
     // gx + gy + gz steps (the cap only guards against malformed input)
     const int max_steps = R.g[0] + R.g[1] + R.g[2] + 3;
@@ -1142,6 +1158,8 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.mode = p->mode;
   R.opaque = p->opaque;
   R.merge = p->merge_curves;
+  R.dist_alpha = p->distance_alpha;
+  R.inv_2r = 0.5f / p->radius;
   R.shading = p->shading;
   R.ka = p->ka;
   R.kd = p->kd;

@@ -19,6 +19,8 @@ struct RenderArgs {
   int32_t ortho, W, H;
   float radius, r2, alpha_stop;
   int32_t mode, opaque, merge, shading;
+  int32_t dist_alpha;             // opacity from the chord length inside the tube
+  float inv_2r;                   // 1 / (2 radius)
   float ka, kd, ks, shin;
   float light[3];
   float* out;

@@ -370,7 +370,8 @@ struct EmitRing {
 template <bool kFloatIn>
 __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
-                                                 int64_t n_curves, const SnapArgs* sap,
+                                                 int64_t n_curves, int64_t curve_base,
+                                                 const SnapArgs* sap,
                                                  GridArgs ga, const uint64_t* slot_off,
                                                  uint64_t* rec_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
   const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
   const uint64_t w0 = slot_off[c], w_end = slot_off[c + 1];
   const uint64_t hi_bits =
-      ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)(c & 0xFFFFFF) << 40);
+      ((uint64_t)(attr ? attr[c] : 255) << 32) | ((uint64_t)((curve_base + c) & 0xFFFFFF) << 40);
   const int64_t gx = ga.g[0], gxy = (int64_t)ga.g[0] * ga.g[1];
   const unsigned long long below = (1ull << lane) - 1ull;
 
@@ -913,11 +914,13 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   if (C > 0) {
     if (float_in)
       hipLaunchKernelGGL((k_emit<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, sad, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         curve_off, attr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     else
       hipLaunchKernelGGL((k_emit<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, sad, ga, slots.as<uint64_t>(), rec.as<uint64_t>(),
+                         curve_off, attr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(),
                          vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
     LS_HIP(hipGetLastError());
   }
@@ -946,10 +949,23 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
     LS_HIP(hipGetLastError());
   }
 
-  // 6. macro-cell occupancy and list statistics; the statistics stay on
-  //    the device after the occupancy words until lineset_info asks for them
+  // 6. macro-cell occupancy and list statistics
+  if ((rc = vox_occupancy(s, st))) return rc;
+  LS_HIP(hipStreamSynchronize(st));
+  return LS_OK;
+}
+
+// Macro-cell occupancy words and list statistics of s->offsets; the
+// statistics stay on the device after the occupancy words until
+// lineset_info asks for them.
+int vox_occupancy(ls_lineset* s, hipStream_t st) {
+  GridArgs ga;
+  for (int a = 0; a < 3; ++a) ga.g[a] = s->grid[a];
+  ga.bins = s->bins;
+  ga.bin_shift = 0;
   for (int a = 0; a < 3; ++a) s->macro[a] = (s->grid[a] + 3) / 4;
   int64_t nm = (int64_t)s->macro[0] * s->macro[1] * s->macro[2];
+  int rc;
   if ((rc = ls_alloc(s, (void**)&s->occupancy, sizeof(uint64_t) * (nm + 2)))) return rc;
   char* stats = reinterpret_cast<char*>(s->occupancy + nm);
   LS_HIP(hipMemsetAsync(stats, 0, 16, st));
@@ -958,7 +974,6 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
                      reinterpret_cast<unsigned long long*>(stats),
                      reinterpret_cast<unsigned int*>(stats + 8));
   LS_HIP(hipGetLastError());
-  LS_HIP(hipStreamSynchronize(st));
   s->stats_pending = true;
   return LS_OK;
 }

@@ -36,7 +36,7 @@ def _items(sets, n_views, seed):
                                   orthographic=bool(rng.integers(0, 2)))[0]
         opaque = bool(v % 2 == 0)
         params = dict(radius=0.4, opaque=opaque, mode=int(v % 5 == 4), shading=int(v % 3 != 0),
-                      merge_curves=True, alpha_stop=0.95)
+                      merge_curves=True, alpha_stop=0.95, distance_alpha=v % 4 == 1)
         out = torch.full((H, W, 4), -1.0, device="cuda")
         items.append((s, cam, luts[0] if opaque else luts[1], out, params))
     return items

@@ -76,6 +76,22 @@ def test_medium_transparent_perspective(medium, shading, merge):
     assert abs(kg["nonempty"] - cnt["nonempty"]) <= 1e-3 * cnt["nonempty"]
 
 
+@pytest.mark.parametrize("mode,shading", [(0, 1), (1, 1), (0, 0)])
+def test_medium_distance_alpha(medium, mode, shading):
+    """Opacity from the chord length inside the tube (both modes)."""
+    ls, ref, s = medium
+    cam = synth.orbit_cameras((96,) * 3, 1, 21 + mode, 190, 140)[0]
+    lut = synth.lut_importance_alpha(0.05, 0.8)
+    g, r, _ = _render_both(s, ref, 96, 32, cam, lut, mode=mode, radius=0.4, opaque=False,
+                           shading=shading, distance_alpha=True)
+    assert r[..., 3].mean() > 0.02
+    U.assert_image_parity(g, r, f"medium distance alpha mode={mode} shading={shading}")
+    # it differs from constant opacity
+    c = L.lineset_render(s, cam, U.dev(lut), mode=mode, radius=0.4, opaque=False, shading=shading)
+    torch.cuda.synchronize()
+    assert np.abs(c.cpu().numpy() - g).max() > 0.05
+
+
 def test_medium_neighbour_mode(medium):
     ls, ref, s = medium
     cam = synth.orbit_cameras((96,) * 3, 1, 5, 160, 120)[0]
