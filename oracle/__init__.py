@@ -52,7 +52,10 @@ class ParamsS(C.Structure):
                 ("lut_rgba", C.POINTER(C.c_float)), ("shading", C.c_int32),
                 ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
                 ("shininess", C.c_float), ("light_dir", C.c_float * 3),
-                ("distance_alpha", C.c_int32)]
+                ("distance_alpha", C.c_int32), ("ao_mode", C.c_int32),
+                ("shadow_mode", C.c_int32), ("ao_rays", C.c_int32), ("ao_radius", C.c_float),
+                ("rep_level", C.c_int32), ("rho", C.POINTER(C.c_double)),
+                ("rep", C.POINTER(C.c_uint32))]
 
 
 class CountersS(C.Structure):
@@ -76,6 +79,9 @@ def lib():
         L.or_lod_levels.restype = C.c_int
         L.or_lod.restype = C.c_int
         L.or_cone.restype = C.c_double
+        L.or_ao_hemi.restype = C.c_double
+        L.or_rep_lines.restype = C.c_int
+        L.or_rep_shadow.restype = C.c_int
         L.or_cone.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32),
                               C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.c_double, C.c_double]
@@ -208,6 +214,45 @@ def shadow_grid(rho, grid, light, aperture=1.0, threads=0):
     return sh
 
 
+def rep_lines(csr: OracleCsr, grid, bins: int) -> np.ndarray:
+    """Representative line codes (uint32, 0xFFFFFFFF for none), all levels
+    flat at lod_levels' offsets."""
+    g = _grid(grid)
+    dims, loff = lod_levels(g)
+    rep = np.zeros(int(loff[-1]), dtype=np.uint32)
+    rc = lib().or_rep_lines(_p(csr.offsets, C.c_uint32), _p(csr.records, C.c_uint64),
+                            _p(g, C.c_int32), C.c_int32(bins), _p(rep, C.c_uint32))
+    if rc < 0:
+        raise MemoryError("or_rep_lines")
+    return rep
+
+
+def rep_shadow(rep, grid, bins, level, radius, x, light) -> bool:
+    g = _grid(grid)
+    rep = np.ascontiguousarray(rep, dtype=np.uint32)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    L = np.ascontiguousarray(light, dtype=np.float64)
+    return bool(lib().or_rep_shadow(_p(rep, C.c_uint32), _p(g, C.c_int32), C.c_int32(bins),
+                                    C.c_int32(level), C.c_double(radius), _p(x, C.c_double),
+                                    _p(L, C.c_double)))
+
+
+def hemi_dirs(n, k: int) -> np.ndarray:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    d = np.zeros((k, 3))
+    lib().or_hemi_dirs(_p(n, C.c_double), C.c_int32(k), _p(d, C.c_double))
+    return d
+
+
+def ao_hemi(rho, grid, x, n, k=16, radius=15.0) -> float:
+    g = _grid(grid)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    return float(lib().or_ao_hemi(_p(rho, C.c_double), _p(g, C.c_int32), _p(x, C.c_double),
+                                  _p(n, C.c_double), C.c_int32(k), C.c_double(radius)))
+
+
 def camera_struct(cam) -> CameraS:
     c = CameraS()
     e, f, r, u = cam.as_arrays()
@@ -263,7 +308,8 @@ def decode(rec: int, bins: int):
 
 def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   lut=None, shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
-                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False):
+                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False, ao_mode=0, shadow_mode=0,
+                  ao_rays=16, ao_radius=15.0, rep_level=1):
     p = ParamsS()
     p.radius = radius
     p.mode = mode
@@ -276,15 +322,25 @@ def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curve
     p.ka, p.kd, p.ks, p.shininess = ka, kd, ks, shininess
     p.light_dir[:] = [float(x) for x in light_dir]
     p.distance_alpha = int(distance_alpha)
+    p.ao_mode, p.shadow_mode, p.ao_rays = int(ao_mode), int(shadow_mode), int(ao_rays)
+    p.ao_radius, p.rep_level = float(ao_radius), int(rep_level)
     return p, lut  # keep lut alive
 
 
 def render(csr: OracleCsr, grid, bins: int, cam, pixels=None, ao=None, sh=None,
-           threads: int = 0, **params):
-    """fp64 image [H, W, 4] (or [n, 4] for a pixel list) plus counters dict."""
+           threads: int = 0, rho=None, rep=None, **params):
+    """fp64 image [H, W, 4] (or [n, 4] for a pixel list) plus counters dict.
+    rho (density pyramid) and rep (representative lines) feed the
+    per-fragment illumination sources of shading 2."""
     g = _grid(grid)
     c = camera_struct(cam)
     p, keep = params_struct(**params)
+    if rho is not None:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        p.rho = _p(rho, C.c_double)
+    if rep is not None:
+        rep = np.ascontiguousarray(rep, dtype=np.uint32)
+        p.rep = _p(rep, C.c_uint32)
     if pixels is not None:
         pix = np.ascontiguousarray(pixels, dtype=np.int64)
         n = pix.shape[0]

@@ -495,14 +495,14 @@ typedef struct {
   int32_t R[3];
 } dda_state;
 
-static void dda_init(dda_state* s, const int32_t grid[3], const float of[3], const float df[3]) {
+static void dda_init(dda_state* s, const int32_t grid[3], const double of[3], const double df[3]) {
   double tn = 0.0, tf = INFINITY;
   s->ok = 0;
-  if (df[0] == 0.0f && df[1] == 0.0f && df[2] == 0.0f) return;
+  if (df[0] == 0.0 && df[1] == 0.0 && df[2] == 0.0) return;
   for (int a = 0; a < 3; ++a) {
     s->R[a] = grid[a];
-    s->o[a] = (double)of[a];
-    double d = (double)df[a];
+    s->o[a] = of[a];
+    double d = df[a];
     /* an axis whose 1/d overflows is treated as parallel to the ray */
     if (d != 0.0 && !isinf(1.0 / d)) {
       s->inv[a] = 1.0 / d;
@@ -520,7 +520,7 @@ static void dda_init(dda_state* s, const int32_t grid[3], const float of[3], con
   }
   if (!(tn < tf)) return;
   for (int a = 0; a < 3; ++a) {
-    double p = (double)df[a] * tn;
+    double p = df[a] * tn;
     p = s->o[a] + p;
     double fl = floor(p);
     int64_t c = (int64_t)fl;
@@ -560,7 +560,8 @@ static int dda_next(dda_state* s, int32_t cell[3], double* t0, double* t1) {
 int64_t or_dda(const int32_t grid[3], const float o[3], const float d[3],
                int32_t* cells, double* t0, double* t1, int64_t cap) {
   dda_state s;
-  dda_init(&s, grid, o, d);
+  double od[3] = {o[0], o[1], o[2]}, dd[3] = {d[0], d[1], d[2]};
+  dda_init(&s, grid, od, dd);
   int64_t n = 0;
   int32_t c[3];
   double a, b;
@@ -652,6 +653,280 @@ int or_capsule(const double o[3], const double d[3], const double a[3],
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section "LoD construction", representative lines. Every voxel gets one
+ * average line: the start points and the end points of its lines are
+ * averaged separately, a line being flipped first when it makes an angle of
+ * more than 90 degrees with the line taken before it (list order, that line
+ * as possibly flipped); each of the two averages is snapped to the closest
+ * bin centre on the voxel's boundary. Then representative lines of two
+ * face-adjacent voxels that both end on their common face are joined: both
+ * endpoints move to the bin holding the mean of the two points. Coarser
+ * levels average the joined lines of the (up to 8) children the same way, in
+ * the parent's frame, and join again.
+ *
+ * Readings: the angle test is a negative dot product of the two direction
+ * vectors; a voxel whose two endpoints lie on one face is not joined, nor is
+ * a neighbour whose two endpoints lie on the common face; children are taken
+ * in order x fastest, then y, then z; a bin boundary belongs to the upper
+ * bin (as in the voxelizer). The representative line of level l has radius
+ * (tube radius) * 2^l in finest-voxel units: the same radius in its own
+ * level's voxel units.
+ *
+ * Exact integer arithmetic: a point of a voxel is held in units of 1/(4N) of
+ * its side (a bin centre is 4k + 2, a face plane 0 or 4N; a child's bin
+ * centre is an integer of the parent), sums of points in int64, squared
+ * distances scaled by n^2 in 128-bit integers. A line's code is the record
+ * layout's low 30 bits (start = entry, end = exit); voxels without lines hold
+ * 0xFFFFFFFF. */
+#define OR_REP_NONE 0xFFFFFFFFu
+
+static void face_axes(int face, int* axis, int* ua, int* wa) {
+  *axis = face >> 1;
+  *ua = (*axis == 0) ? 1 : 0;
+  *wa = (*axis == 2) ? 1 : 2;
+}
+
+/* bin centre of a 15-bit endpoint code, in units of 1/(4N) of its voxel */
+static void end_units(uint32_t code, int32_t bins, int64_t p[3]) {
+  int axis, ua, wa;
+  int face = (int)(code & 7u);
+  face_axes(face, &axis, &ua, &wa);
+  p[axis] = (face & 1) ? 4 * (int64_t)bins : 0;
+  p[ua] = 4 * (int64_t)((code >> 3) & 63u) + 2;
+  p[wa] = 4 * (int64_t)((code >> 9) & 63u) + 2;
+}
+
+/* bin index k in [0, N) minimising |S - n (4k + 2)|, the lowest on ties */
+static int nearest_bin(int64_t S, int64_t n, int32_t bins, __int128* d2) {
+  int best = 0;
+  __int128 bd = -1;
+  for (int k = 0; k < bins; ++k) {
+    __int128 d = (__int128)S - (__int128)n * (4 * (int64_t)k + 2);
+    __int128 q = d * d;
+    if (bd < 0 || q < bd) {
+      bd = q;
+      best = k;
+    }
+  }
+  *d2 = bd;
+  return best;
+}
+
+/* Closest bin centre on the voxel boundary to the point S / n (units of
+ * 1/(4N)); 15-bit endpoint code. On one face the squared distance is the
+ * plane term plus one term per in-plane axis, so the face's closest centre
+ * takes the closest bin on each axis; faces are compared in order, the first
+ * one kept on ties. */
+static uint32_t snap_point(const int64_t S[3], int64_t n, int32_t bins) {
+  __int128 best = -1;
+  uint32_t code = 0;
+  for (int f = 0; f < 6; ++f) {
+    int axis, ua, wa;
+    face_axes(f, &axis, &ua, &wa);
+    __int128 da = (__int128)S[axis] - (__int128)n * ((f & 1) ? 4 * (int64_t)bins : 0);
+    __int128 du2, dw2;
+    int bu = nearest_bin(S[ua], n, bins, &du2);
+    int bw = nearest_bin(S[wa], n, bins, &dw2);
+    __int128 d2 = da * da + du2 + dw2;
+    if (best < 0 || d2 < best) {
+      best = d2;
+      code = (uint32_t)f | ((uint32_t)bu << 3) | ((uint32_t)bw << 9);
+    }
+  }
+  return code;
+}
+
+typedef struct {
+  int64_t S[3], E[3], prev[3];
+  int64_t n;
+} rep_acc;
+
+static void rep_add(rep_acc* r, const int64_t a_in[3], const int64_t b_in[3]) {
+  int64_t a[3], b[3], dir[3];
+  for (int q = 0; q < 3; ++q) { a[q] = a_in[q]; b[q] = b_in[q]; }
+  if (r->n > 0) {
+    int64_t dot = 0;
+    for (int q = 0; q < 3; ++q) dot += (b[q] - a[q]) * r->prev[q];
+    if (dot < 0) {
+      for (int q = 0; q < 3; ++q) { int64_t t = a[q]; a[q] = b[q]; b[q] = t; }
+    }
+  }
+  for (int q = 0; q < 3; ++q) {
+    dir[q] = b[q] - a[q];
+    r->S[q] += a[q];
+    r->E[q] += b[q];
+    r->prev[q] = dir[q];
+  }
+  r->n++;
+}
+
+static uint32_t rep_code(const rep_acc* r, int32_t bins) {
+  if (r->n == 0) return OR_REP_NONE;
+  uint32_t s = snap_point(r->S, r->n, bins);
+  uint32_t e = snap_point(r->E, r->n, bins);
+  return s | (e << 15);
+}
+
+/* Joins representative lines across shared faces (pre -> out, one level). */
+static void rep_connect(const uint32_t* pre, uint32_t* out, const int32_t dim[3]) {
+  for (int32_t z = 0; z < dim[2]; ++z)
+    for (int32_t y = 0; y < dim[1]; ++y)
+      for (int32_t x = 0; x < dim[0]; ++x) {
+        int64_t v = x + (int64_t)dim[0] * (y + (int64_t)dim[1] * z);
+        uint32_t code = pre[v];
+        if (code == OR_REP_NONE) {
+          out[v] = code;
+          continue;
+        }
+        uint32_t ends[2] = {code & 0x7FFFu, (code >> 15) & 0x7FFFu};
+        int f0 = (int)(ends[0] & 7u), f1 = (int)(ends[1] & 7u);
+        if (f0 != f1) {
+          for (int e = 0; e < 2; ++e) {
+            int f = (int)(ends[e] & 7u), axis = f >> 1;
+            int32_t c[3] = {x, y, z};
+            c[axis] += (f & 1) ? 1 : -1;
+            if (c[axis] < 0 || c[axis] >= dim[axis]) continue;
+            uint32_t nb = pre[c[0] + (int64_t)dim[0] * (c[1] + (int64_t)dim[1] * c[2])];
+            if (nb == OR_REP_NONE) continue;
+            uint32_t n0 = nb & 0x7FFFu, n1 = (nb >> 15) & 0x7FFFu;
+            int g = f ^ 1;
+            uint32_t other;
+            if ((int)(n0 & 7u) == g && (int)(n1 & 7u) != g) other = n0;
+            else if ((int)(n1 & 7u) == g && (int)(n0 & 7u) != g) other = n1;
+            else continue;
+            uint32_t bu = (((ends[e] >> 3) & 63u) + ((other >> 3) & 63u) + 1u) >> 1;
+            uint32_t bw = (((ends[e] >> 9) & 63u) + ((other >> 9) & 63u) + 1u) >> 1;
+            ends[e] = (uint32_t)f | (bu << 3) | (bw << 9);
+          }
+        }
+        out[v] = ends[0] | (ends[1] << 15);
+      }
+}
+
+int or_rep_lines(const uint32_t* offsets, const uint64_t* records, const int32_t grid[3],
+                 int32_t bins, uint32_t* rep) {
+  int32_t dims[96];
+  int64_t loff[33];
+  int nl = or_lod_levels(grid, dims, loff);
+  uint32_t* pre = (uint32_t*)malloc((size_t)loff[1] * sizeof(uint32_t));
+  if (!pre) return -2;
+  /* level 0 from the voxels' line lists */
+  int64_t nvox = loff[1];
+  for (int64_t v = 0; v < nvox; ++v) {
+    rep_acc r;
+    memset(&r, 0, sizeof(r));
+    for (uint32_t k = offsets[v]; k < offsets[v + 1]; ++k) {
+      int64_t a[3], b[3];
+      end_units((uint32_t)(records[k] & 0x7FFFu), bins, a);
+      end_units((uint32_t)((records[k] >> 15) & 0x7FFFu), bins, b);
+      rep_add(&r, a, b);
+    }
+    pre[v] = rep_code(&r, bins);
+  }
+  rep_connect(pre, rep, dims);
+  /* coarser levels from the joined lines of the children */
+  for (int lv = 1; lv < nl; ++lv) {
+    const int32_t* dc = dims + 3 * (lv - 1);
+    const int32_t* dp = dims + 3 * lv;
+    for (int32_t z = 0; z < dp[2]; ++z)
+      for (int32_t y = 0; y < dp[1]; ++y)
+        for (int32_t x = 0; x < dp[0]; ++x) {
+          rep_acc r;
+          memset(&r, 0, sizeof(r));
+          for (int k = 0; k < 8; ++k) {
+            int32_t off[3] = {k & 1, (k >> 1) & 1, k >> 2};
+            int32_t cx = 2 * x + off[0], cy = 2 * y + off[1], cz = 2 * z + off[2];
+            if (cx >= dc[0] || cy >= dc[1] || cz >= dc[2]) continue;
+            uint32_t cc = rep[loff[lv - 1] + cx + (int64_t)dc[0] * (cy + (int64_t)dc[1] * cz)];
+            if (cc == OR_REP_NONE) continue;
+            int64_t a[3], b[3];
+            end_units(cc & 0x7FFFu, bins, a);
+            end_units((cc >> 15) & 0x7FFFu, bins, b);
+            /* child units 1/(4N) of the child = 1/(8N) of the parent: halve
+             * (bin centres and planes are even) and add the child's offset */
+            for (int q = 0; q < 3; ++q) {
+              a[q] = a[q] / 2 + (int64_t)off[q] * 2 * bins;
+              b[q] = b[q] / 2 + (int64_t)off[q] * 2 * bins;
+            }
+            rep_add(&r, a, b);
+          }
+          pre[x + (int64_t)dp[0] * (y + (int64_t)dp[1] * z)] = rep_code(&r, bins);
+        }
+    rep_connect(pre, rep + loff[lv], dp);
+  }
+  free(pre);
+  return nl;
+}
+
+/* Section "Shadow simulation", first approach: a shadow ray from the point x
+ * (finest-voxel units) towards the light walks the voxels of level `level`
+ * and is tested against each voxel's representative line, a tube of radius
+ * `radius` in that level's voxel units (so thicker than the lines it stands
+ * for). Returns 1 when the ray enters one of them at a positive distance (a
+ * line the point already lies inside does not shadow it), else 0. */
+int or_rep_shadow(const uint32_t* rep, const int32_t grid[3], int32_t bins, int32_t level,
+                  double radius, const double x[3], const double light[3]) {
+  int32_t dims[96];
+  int64_t loff[33];
+  int nl = or_lod_levels(grid, dims, loff);
+  if (level < 0 || level >= nl) return 0;
+  const int32_t* dm = dims + 3 * level;
+  double scale = ldexp(1.0, -level);
+  double o[3] = {x[0] * scale, x[1] * scale, x[2] * scale};
+  double d[3] = {light[0], light[1], light[2]};
+  dda_state s;
+  dda_init(&s, dm, o, d);
+  int32_t cell[3];
+  double t0, t1;
+  while (dda_next(&s, cell, &t0, &t1)) {
+    uint32_t code = rep[loff[level] + cell[0] + (int64_t)dm[0] * (cell[1] + (int64_t)dm[1] * cell[2])];
+    if (code == OR_REP_NONE) continue;
+    double A[3], B[3];
+    decode_code(code & 0x7FFFu, bins, A);
+    decode_code((code >> 15) & 0x7FFFu, bins, B);
+    for (int q = 0; q < 3; ++q) { A[q] += cell[q]; B[q] += cell[q]; }
+    double ti, to;
+    if (or_capsule(o, d, A, B, radius, &ti, &to, NULL) && ti > 0.0) return 1;
+  }
+  return 0;
+}
+
+/* Section "Ambient occlusion", first approach: from a visible point, rays
+ * into the hemisphere around the surface normal sample the finest density
+ * level (trilinear), one sample per voxel of distance, accumulating until the
+ * density reaches 1 or the ray passes the radius of influence or leaves the
+ * grid; the occlusion is averaged over the rays. Directions (reading): k
+ * points of equal area, heights z_i = 1 - (i + 0.5)/k over the hemisphere,
+ * azimuths i times the golden angle pi (3 - sqrt 5), in the orthonormal frame
+ * (t1, t2, n) of Duff et al., "Building an Orthonormal Basis, Revisited"
+ * (JCGT 2017), with the sign taken as +1 for n_z >= 0. */
+void or_hemi_dirs(const double n[3], int32_t k, double* dirs) {
+  double sgn = n[2] >= 0.0 ? 1.0 : -1.0;
+  double a = -1.0 / (sgn + n[2]);
+  double b = n[0] * n[1] * a;
+  double t1[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+  double t2[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+  double ga = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+  for (int32_t i = 0; i < k; ++i) {
+    double z = 1.0 - ((double)i + 0.5) / (double)k;
+    double r = sqrt(1.0 - z * z);
+    double ph = ga * (double)i;
+    double cx = r * cos(ph), cy = r * sin(ph);
+    for (int q = 0; q < 3; ++q) dirs[3 * i + q] = cx * t1[q] + cy * t2[q] + z * n[q];
+  }
+}
+
+double or_ao_hemi(const double* rho, const int32_t grid[3], const double x[3],
+                  const double n[3], int32_t k, double radius) {
+  double dirs[3 * 256];
+  if (k < 1 || k > 256) return 1.0;
+  or_hemi_dirs(n, k, dirs);
+  double sum = 0.0;
+  for (int32_t i = 0; i < k; ++i) sum += or_cone(rho, grid, x, dirs + 3 * i, radius, 0.0);
+  return 1.0 - sum / (double)k;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Rendering (sections "Line Raycasting", "Rendering effects", "Transparency
  * rendering"). Per visited voxel: test the candidate lines, sort the accepted
  * hits by (entry t, record index), then per hit in that order: per-curve
@@ -737,7 +1012,7 @@ static void render_pixel(const rctx* c, int32_t i, int32_t j, double out[4], or_
   open_iv* open = NULL;
   int64_t n_open = 0, cap_open = 0;
   dda_state s;
-  dda_init(&s, c->grid, of, df);
+  dda_init(&s, c->grid, o, d);
   int32_t cell[3];
   double t0, t1;
   int done = 0;
@@ -807,8 +1082,17 @@ static void render_pixel(const rctx* c, int32_t i, int32_t j, double out[4], or_
         double spec = (double)p->ks * pow(ndv, (double)p->shininess);
         for (int q = 0; q < 3; ++q) col[q] = base[q] * ((double)p->ka + (double)p->kd * ndv) + spec;
       } else {
-        double aov = trilinear_grid(c->ao, G, H->x);
-        double shv = trilinear_grid(c->sh, G, H->x);
+        double aov, shv;
+        if (p->ao_mode == 1)
+          aov = or_ao_hemi(p->rho, G, H->x, H->n, p->ao_rays, (double)p->ao_radius);
+        else
+          aov = trilinear_grid(c->ao, G, H->x);
+        if (p->shadow_mode == 1)
+          shv = 1.0 - or_cone(p->rho, G, H->x, L, INFINITY, 1.0);
+        else if (p->shadow_mode == 2)
+          shv = or_rep_shadow(p->rep, G, c->bins, p->rep_level, (double)p->radius, H->x, L) ? 0.0 : 1.0;
+        else
+          shv = trilinear_grid(c->sh, G, H->x);
         double ndl = dot3(H->n, L);
         if (ndl < 0) ndl = 0;
         double ndh = dot3(H->n, h);
@@ -837,7 +1121,13 @@ int or_render(const uint32_t* offsets, const uint64_t* records, const int32_t gr
               const double* sh, const int64_t* pixels, int64_t n_pixels, double* rgba,
               or_counters* counters, int32_t n_threads) {
   rctx c = {offsets, records, grid, bins, cam, p, ao, sh};
-  if (p->shading == 2 && (!ao || !sh)) return -1;
+  if (p->shading == 2) {
+    if (p->ao_mode == 0 && !ao) return -1;
+    if (p->shadow_mode == 0 && !sh) return -1;
+    if ((p->ao_mode == 1 || p->shadow_mode == 1) && !p->rho) return -1;
+    if (p->shadow_mode == 2 && !p->rep) return -1;
+    if (p->ao_mode == 1 && p->ao_rays < 1) return -1;
+  }
   int64_t W = cam->width, H = cam->height;
   int64_t n = pixels ? n_pixels : W * H;
   int64_t kv = 0, kn = 0, kt = 0, kh = 0, kf = 0;

@@ -70,6 +70,22 @@ int or_ao_grid(const double* rho, const int32_t grid[3], int32_t n_cones,
 int or_shadow_grid(const double* rho, const int32_t grid[3], const double light[3],
                    double aperture, double* sh, int32_t n_threads);
 
+/* Section "LoD construction": one representative line per voxel and level
+ * (code = record bits 0..29, 0xFFFFFFFF for none), levels flat at the
+ * density pyramid's level offsets. Returns the level count. */
+int or_rep_lines(const uint32_t* offsets, const uint64_t* records, const int32_t grid[3],
+                 int32_t bins, uint32_t* rep);
+/* Section "Shadow simulation", first approach: 1 if the ray from x towards
+ * `light` enters a representative line of `level` (radius in that level's
+ * voxel units) at a positive distance. */
+int or_rep_shadow(const uint32_t* rep, const int32_t grid[3], int32_t bins, int32_t level,
+                  double radius, const double x[3], const double light[3]);
+/* Section "Ambient occlusion", first approach: k hemisphere directions
+ * around n, and 1 - mean occlusion of level-0 rays of the given radius. */
+void or_hemi_dirs(const double n[3], int32_t k, double* dirs /* [k][3] */);
+double or_ao_hemi(const double* rho, const int32_t grid[3], const double x[3],
+                  const double n[3], int32_t k, double radius);
+
 /* Section "Line Raycasting" and "Rendering effects". */
 typedef struct {
   float eye[3], forward[3], right[3], up[3];
@@ -87,6 +103,16 @@ typedef struct {
   float ka, kd, ks, shininess;
   float light_dir[3];    /* towards the light, unit length */
   int32_t distance_alpha; /* 1: opacity from the chord length inside the tube */
+  /* shading 2, view-dependent sources (sections "Shadow simulation",
+   * "Ambient occlusion"): */
+  int32_t ao_mode;       /* 0 per-voxel AO grid, 1 per-fragment hemisphere rays on level 0 */
+  int32_t shadow_mode;   /* 0 per-voxel shadow grid, 1 per-fragment cone,
+                            2 shadow ray against the representative lines */
+  int32_t ao_rays;       /* hemisphere rays (ao_mode 1) */
+  float ao_radius;       /* radius of influence (ao_mode 1), voxels */
+  int32_t rep_level;     /* level of the representative lines (shadow_mode 2) */
+  const double* rho;     /* density pyramid, levels flat (ao_mode 1, shadow_mode 1) */
+  const uint32_t* rep;   /* representative lines, levels flat (shadow_mode 2) */
 } or_params;
 
 typedef struct {
