@@ -770,6 +770,80 @@ __device__ inline double owner_ref(const Ray& ray, const int32_t w[3], double id
   return s * idd;
 }
 
+// Ray vs capsule for the neighbour mode, as absolute ray parameters. The
+// cylinder is intersected in the owner voxel's frame (origin at the ray point
+// tr); each joint sphere in a frame of its own, with the origin at the ray
+// point nearest its centre c = owner corner + endpoint (exact in fp32). Two
+// consecutive lines of a curve share that sphere: a ray entering through it
+// then gets bit-identical entry parameters from both lines, and their order
+// falls to the record index, as with exact arithmetic.
+__device__ inline bool capsule_abs(const Ray& ray, double tr, const float q[3], const int32_t w[3],
+                                   float dd, float inv_dd, double idd, const float a[3],
+                                   const float b[3], float r2, double& t_in, double& t_out) {
+  #pragma clang fp contract(fast)
+  double lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float* p = e ? b : a;
+    double c[3], tc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c[k] = (double)w[k] + (double)p[k];
+      tc += (c[k] - ray.od[k]) * (double)ray.d[k];
+    }
+    tc *= idd;
+    float qs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) qs[k] = (float)(fma(tc, (double)ray.d[k], ray.od[k]) - c[k]);
+    const float B = dot3(qs, ray.d), C = dot3(qs, qs) - r2;
+    const float disc = B * B - dd * C;
+    if (disc >= 0.f) {
+      const float s = __builtin_sqrtf(disc);
+      lo = fmin(lo, tc + (double)((-B - s) * inv_dd));
+      hi = fmax(hi, tc + (double)((-B + s) * inv_dd));
+    }
+  }
+  float ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  float oa[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+  float L2 = dot3(ba, ba);
+  float iL2 = rcp(L2);
+  float dba = dot3(ray.d, ba), oba = dot3(oa, ba);
+  float kd = dba * iL2, ko = oba * iL2;
+  float dp[3] = {ray.d[0] - kd * ba[0], ray.d[1] - kd * ba[1], ray.d[2] - kd * ba[2]};
+  float op[3] = {oa[0] - ko * ba[0], oa[1] - ko * ba[1], oa[2] - ko * ba[2]};
+  float A = dot3(dp, dp);
+  if (A > 0.f) {
+    float B = dot3(op, dp), C = dot3(op, op) - r2;
+    float disc = B * B - A * C;
+    if (disc >= 0.f) {
+      float s = __builtin_sqrtf(disc);
+      float iA = rcp(A);
+      float c0 = (-B - s) * iA, c1 = (-B + s) * iA;
+      float s0, s1;
+      if (dba != 0.f) {
+        float idba = rcp(dba);
+        float u0 = -oba * idba, u1 = (L2 - oba) * idba;
+        s0 = fminf(u0, u1);
+        s1 = fmaxf(u0, u1);
+      } else if (oba >= 0.f && oba <= L2) {
+        s0 = -INFINITY;
+        s1 = INFINITY;
+      } else {
+        s0 = INFINITY;
+        s1 = -INFINITY;
+      }
+      float e0 = fmaxf(c0, s0), e1 = fminf(c1, s1);
+      if (e0 <= e1) {
+        lo = fmin(lo, tr + (double)e0);
+        hi = fmax(hi, tr + (double)e1);
+      }
+    }
+  }
+  t_in = lo;
+  t_out = hi;
+  return lo <= hi;
+}
+
 __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderArgs& R, const float4* lut_lds, const Ray& ray, const Shade& S, float dd,
                                    float inv_dd, double idd, double t1, Accum& acc, Counts& cnt) {
   double last_t = -INFINITY;
@@ -791,16 +865,16 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       local_origin(ray, tr, w, q);
       for (uint32_t k = lo; k < hi; ++k) {
         const uint64_t rec = R.records[k];
-        float a[3], b[3], si, so;
+        float a[3], b[3];
         decode_point((uint32_t)(rec & 0x7FFFu), R.inv_bins, a);
         decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
         cnt.tested++;
-        if (!capsule(q, ray.d, dd, inv_dd, a, b, R.r2, si, so)) continue;
-        const double ti = tr + (double)si;
+        double ti, to;
+        if (!capsule_abs(ray, tr, q, w, dd, inv_dd, idd, a, b, R.r2, ti, to)) continue;
         if (!(ti >= ray.t0 && ti < t1)) continue;
         if (!first && !HitBuf<double>::less(last_t, last_i, ti, k)) continue;
         if (first) cnt.hits++;
-        buf.insert(ti, (float)(tr + (double)so - ti), k, (uint32_t)nb, rec);
+        buf.insert(ti, (float)(to - ti), k, (uint32_t)nb, rec);
       }
     }
     last_t = buf.t[kSortSlots - 1];
