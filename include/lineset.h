@@ -310,6 +310,18 @@ void lineset_batch_destroy(ls_batch_t batch);   /* waits for the device */
 /* One-shot: create (default plan, no graph), render, synchronise, destroy. */
 int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same one-shot
+ * batch as lineset_render_batch (same default plan, same images), with its
+ * queue counters, tile starts and view descriptors in a fixed device array of
+ * the library (about 70 KB per GPU, held until the process ends) instead of
+ * allocated buffers. Calls no hipMalloc / hipFree. At most 256 views per call
+ * (LS_EINVAL beyond); the views' sets, LUTs and outputs are the caller's as
+ * in lineset_render_batch. Synchronises hip_stream before returning. Every
+ * call on one GPU uses that GPU's one array: calls that overlap on the same
+ * GPU (from several host threads) race and must be serialised by the caller. */
+int lineset_render_batch_static(const ls_view* views, int32_t n_views, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Render server: keeps voxelized line sets resident, admits render requests
  * by an HBM budget and batches them continuously (section "GPU

@@ -378,6 +378,7 @@ def _bind_batch(L):
     L.lineset_batch_destroy.argtypes = [C.c_void_p]
     L.lineset_batch_destroy.restype = None
     L.lineset_render_batch.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_void_p]
+    L.lineset_render_batch_static.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_void_p]
     L._batch_bound = True
 
 
@@ -433,6 +434,15 @@ def lineset_render_batch(items, stream=None):
     _bind_batch(L)
     views = make_views(items)
     _check(L.lineset_render_batch(views, len(items), _stream(stream)))
+
+
+def lineset_render_batch_static(items, stream=None):
+    """lineset_render_batch without device allocation (library-owned fixed
+    scratch, at most 256 views)."""
+    L = lib()
+    _bind_batch(L)
+    views = make_views(items)
+    _check(L.lineset_render_batch_static(views, len(items), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -170,6 +170,48 @@ int capture(ls_batch* b) {
   return LS_OK;
 }
 
+// Allocation-free one-shot batch (lineset_render_batch_static): queue
+// counters, tile starts and view descriptors live in one file-scope device
+// array per GPU instead of hipMalloc'd buffers.
+constexpr int kStaticViews = 256;
+constexpr size_t kStaticQueueOff = 0;
+constexpr size_t kStaticTileOff = 256;  // after the queue words
+constexpr size_t kStaticArgsOff =
+    (kStaticTileOff + sizeof(int32_t) * (kStaticViews + 1) + 255) / 256 * 256;
+constexpr size_t kStaticBytes = kStaticArgsOff + sizeof(RenderArgs) * kStaticViews;
+static_assert(sizeof(unsigned) * 8 <= kStaticTileOff, "queue words overlap the tile starts");
+
+constexpr int kStaticDevices = 64;
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kStaticDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the array's host-side name is not an address).
+int static_scratch(int dev, unsigned char** out);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+int static_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kStaticDevices) {
+    ls_set_error("lineset_render_batch_static: device %d out of range", dev);
+    return LS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      ls_set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return LS_EDEVICE;
+    }
+    g_static_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_static_ptr[dev];
+  return LS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -293,6 +335,58 @@ void lineset_batch_destroy(ls_batch_t b) {
   free_batch(b);
   if (cur != b->device) (void)hipSetDevice(cur);
   delete b;
+}
+
+int lineset_render_batch_static(const ls_view* views, int32_t n_views, void* hip_stream) {
+  if (!views || n_views < 1 || n_views > kStaticViews) {
+    ls_set_error("lineset_render_batch_static: need 1 .. %d views", kStaticViews);
+    return LS_EINVAL;
+  }
+  int rc;
+  for (int v = 0; v < n_views; ++v)
+    if ((rc = check_render(views[v].set, &views[v].cam, &views[v].params, views[v].rgba_out))) {
+      return rc;
+    }
+  int dev = 0;
+  LS_HIP(hipGetDevice(&dev));
+  unsigned char* base = nullptr;
+  if ((rc = static_scratch(dev, &base))) return rc;
+  // Host staging on the stack (no heap): the copies below read it before the
+  // stream synchronisation at the end returns.
+  RenderArgs args[kStaticViews];
+  int32_t tile_start[kStaticViews + 1];
+  BatchPlan plan{2, 2, 0};
+  if ((rc = plan_blocks(plan.wx, plan.wy, 1, &plan.blocks))) return rc;
+  int64_t total = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const ls_view& x = views[v];
+    make_render_args(x.set, &x.cam, &x.params, x.rgba_out, plan.wx, plan.wy, nullptr, &args[v]);
+    tile_start[v] = (int32_t)total;
+    total += args[v].n_tiles;
+  }
+  if (total > (1ll << 30)) {
+    ls_set_error("lineset_render_batch_static: batch has too many tiles");
+    return LS_EINVAL;
+  }
+  tile_start[n_views] = (int32_t)total;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  unsigned* d_queue = reinterpret_cast<unsigned*>(base + kStaticQueueOff);
+  int32_t* d_tiles = reinterpret_cast<int32_t*>(base + kStaticTileOff);
+  RenderArgs* d_args = reinterpret_cast<RenderArgs*>(base + kStaticArgsOff);
+  LS_HIP(hipMemcpyAsync(d_args, args, sizeof(RenderArgs) * n_views, hipMemcpyHostToDevice, st));
+  LS_HIP(hipMemcpyAsync(d_tiles, tile_start, sizeof(int32_t) * (n_views + 1),
+                        hipMemcpyHostToDevice, st));
+  rc = fill_u32(d_queue, 0u, 8, st);
+  if (!rc) {
+    rc = launch_render_batch(d_args, d_tiles, n_views, make_queues((int)total), d_queue, plan,
+                             false, st);
+  }
+  // Synchronise on every path from here: the copies read the stack arrays.
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    ls_set_error("lineset_render_batch_static: stream synchronisation failed");
+    rc = LS_EDEVICE;
+  }
+  return rc;
 }
 
 int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream) {
