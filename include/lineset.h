@@ -163,6 +163,19 @@ void lineset_destroy(ls_lineset_t set);
  *           (s_max = ao_radius)
  *   sh[v] = 1 - occlusion towards light_dir (s_max = infinity)
  *   lut_rgba   device, float [256][4] straight alpha
+ *
+ * Optionally one representative line per voxel of every level (section "LoD
+ * construction"), exported as uint32 codes (LS_EXPORT_REP_LINES, levels flat
+ * at level_off; the record layout's low 30 bits with start = entry, end =
+ * exit; 0xFFFFFFFF where a voxel has no lines): the start and end points of
+ * the voxel's lines are averaged separately, a line flipped first when its
+ * direction has a negative dot product with the previous line (list order,
+ * as flipped); each average goes to the closest bin centre on the boundary
+ * (first face, lowest bins on ties); then two face-adjacent voxels with one
+ * endpoint each on their common face move both to the bin of the points'
+ * mean (a mean on a bin boundary to the upper bin). Level l + 1 averages the
+ * joined lines of its children (x fastest, then y, z) in its own frame and
+ * joins again. Exact integer arithmetic; bit-identical to the definition.
  * Errors: LS_EINVAL (bad cone count, radius, aperture or light), LS_ENOMEM;
  * LS_EUNSUPPORTED when a cone needs more than 48 samples or sample distances
  * not exact in fp32 (apertures far below 1). */
@@ -175,6 +188,7 @@ typedef struct {
   float cone_aperture;       /* default 1: the cone subtends one voxel at s = 1 */
   int32_t build_shadow;
   float light_dir[3];        /* unit vector towards a directional light */
+  int32_t build_rep_lines;   /* 1: representative lines of every level (see below) */
 } ls_lod_desc;
 
 int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_stream);
@@ -202,6 +216,21 @@ int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_strea
  *   shading 1: rgb (ka + kd |n.v|) + ks |n.v|^shininess
  *   shading 2: rgb (ka AO(x) + kd SH(x) max(0, n.L)) + ks SH(x) max(0, n.h)^shininess
  * (v towards the eye, h = normalize(L + v), AO/SH trilinear at the entry).
+ * In shading 2 the AO and shadow factors come from (view-dependent
+ * illumination, sections "Shadow simulation" and "Ambient occlusion"):
+ *   ao_mode 0: the per-voxel AO grid, trilinear at the entry point x;
+ *   ao_mode 1: per fragment, ao_rays hemisphere rays about the tube normal n
+ *     (equal-area heights 1 - (i + 0.5)/ao_rays, azimuth i * pi (3 - sqrt 5),
+ *     in the Duff et al. orthonormal frame of n), each sampling the finest
+ *     density level at distances 1, 2, ... < ao_radius until the density sum
+ *     reaches 1; AO = 1 - mean occlusion;
+ *   shadow_mode 0: the per-voxel shadow grid at x;
+ *   shadow_mode 1: per fragment, 1 - the cone occlusion from x towards
+ *     light_dir (aperture 1, as the shadow grid's cones);
+ *   shadow_mode 2: per fragment, a shadow ray from x towards light_dir walks
+ *     level rep_level and is tested against the representative lines there,
+ *     tubes of `radius` in that level's voxel units: 0 if it enters one at a
+ *     positive distance, else 1.
  * Premultiplied front-to-back: C += (1 - A) a c, A += (1 - A) a; the ray stops
  * once A >= alpha_stop (opaque lines: a = 1). Opacity a = lut alpha, or with
  * distance_alpha (section "Transparency rendering": opacity dependent on the
@@ -211,7 +240,8 @@ int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_strea
  *   lut_rgba   device, float [256][4] straight alpha
  *   rgba_out   device, float [height][width][4], premultiplied (C, A)
  * Errors: LS_EINVAL for a zero or negative size, radius <= 0 (or >= 1 in
- * mode 1), a zero forward/direction, shading 2 without illumination grids. */
+ * mode 1), a zero forward/direction, shading 2 without the grids, pyramid or
+ * representative lines its sources need, ao_rays outside [1, 256]. */
 typedef struct {
   float eye[3], forward[3], right[3], up[3];
   int32_t orthographic, width, height;
@@ -228,6 +258,12 @@ typedef struct {
   float ka, kd, ks, shininess;
   float light_dir[3];
   int32_t distance_alpha;    /* 1: opacity from the chord length (see below) */
+  int32_t ao_mode;           /* shading 2: 0 per-voxel grid, 1 per-fragment hemisphere */
+  int32_t shadow_mode;       /* shading 2: 0 per-voxel grid, 1 per-fragment cone,
+                                2 representative-line shadow ray */
+  int32_t ao_rays;           /* ao_mode 1: rays per fragment (default 16) */
+  float ao_radius;           /* ao_mode 1: radius of influence in voxels (default 15) */
+  int32_t rep_level;         /* shadow_mode 2: pyramid level of the representative lines */
 } ls_render_params;
 
 int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,
@@ -314,7 +350,7 @@ int lineset_render_batch(const ls_view* views, int32_t n_views, void* hip_stream
  * tight serving loops, harnesses that forbid hipMalloc): the same one-shot
  * batch as lineset_render_batch (same default plan, same images), with its
  * queue counters, tile starts and view descriptors in a fixed device array of
- * the library (about 70 KB per GPU, held until the process ends) instead of
+ * the library (about 80 KB per GPU, held until the process ends) instead of
  * allocated buffers. Calls no hipMalloc / hipFree. At most 256 views per call
  * (LS_EINVAL beyond); the views' sets, LUTs and outputs are the caller's as
  * in lineset_render_batch. Synchronises hip_stream before returning. Every
@@ -433,6 +469,7 @@ typedef struct {
   int64_t max_list;          /* longest per-voxel list */
   int32_t n_levels;          /* density pyramid levels (0 before build_lod) */
   int32_t has_ao, has_shadow;
+  int32_t has_rep_lines;
   int32_t level_dims[32][3];
   int64_t level_off[33];
   double lo_scale[4];        /* grid set-up of xyz input: lo[3], S */
@@ -448,7 +485,8 @@ enum {
   LS_EXPORT_LOD_LEN = 3,
   LS_EXPORT_LOD_RHO = 4,
   LS_EXPORT_AO = 5,          /* float [voxels] */
-  LS_EXPORT_SHADOW = 6       /* float [voxels] */
+  LS_EXPORT_SHADOW = 6,      /* float [voxels] */
+  LS_EXPORT_REP_LINES = 7    /* uint32, all levels flat (level_off) */
 };
 
 /* Copies one buffer of the set into `dst` (host or device). Errors:

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblineset.so")
 
 LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EUNSUPPORTED, LS_EBUSY, LS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
-EXPORT_OFFSETS, EXPORT_RECORDS, EXPORT_LOD_COUNT, EXPORT_LOD_LEN, EXPORT_LOD_RHO, EXPORT_AO, EXPORT_SHADOW = range(7)
+(EXPORT_OFFSETS, EXPORT_RECORDS, EXPORT_LOD_COUNT, EXPORT_LOD_LEN, EXPORT_LOD_RHO, EXPORT_AO,
+ EXPORT_SHADOW, EXPORT_REP_LINES) = range(8)
 
 
 class LinesetError(RuntimeError):
@@ -36,7 +37,8 @@ class VoxelizeDesc(C.Structure):
 class LodDesc(C.Structure):
     _fields_ = [("lut_rgba", C.c_void_p), ("opaque", C.c_int32), ("build_ao", C.c_int32),
                 ("ao_cones", C.c_int32), ("ao_radius", C.c_float), ("cone_aperture", C.c_float),
-                ("build_shadow", C.c_int32), ("light_dir", C.c_float * 3)]
+                ("build_shadow", C.c_int32), ("light_dir", C.c_float * 3),
+                ("build_rep_lines", C.c_int32)]
 
 
 class CameraS(C.Structure):
@@ -50,7 +52,9 @@ class RenderParams(C.Structure):
                 ("alpha_stop", C.c_float), ("merge_curves", C.c_int32), ("lut_rgba", C.c_void_p),
                 ("shading", C.c_int32), ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
                 ("shininess", C.c_float), ("light_dir", C.c_float * 3),
-                ("distance_alpha", C.c_int32)]
+                ("distance_alpha", C.c_int32), ("ao_mode", C.c_int32),
+                ("shadow_mode", C.c_int32), ("ao_rays", C.c_int32), ("ao_radius", C.c_float),
+                ("rep_level", C.c_int32)]
 
 
 class RenderCounters(C.Structure):
@@ -68,7 +72,8 @@ class Info(C.Structure):
                 ("n_vertices", C.c_int64), ("n_records", C.c_int64),
                 ("n_record_slots", C.c_int64), ("nonempty_voxels", C.c_int64),
                 ("max_list", C.c_int64), ("n_levels", C.c_int32), ("has_ao", C.c_int32),
-                ("has_shadow", C.c_int32), ("level_dims", (C.c_int32 * 3) * 32),
+                ("has_shadow", C.c_int32), ("has_rep_lines", C.c_int32),
+                ("level_dims", (C.c_int32 * 3) * 32),
                 ("level_off", C.c_int64 * 33), ("lo_scale", C.c_double * 4),
                 ("device_bytes", C.c_size_t)]
 
@@ -230,7 +235,7 @@ def lineset_update(ls: LineSet, remove=None, curve_off=None, xyz=None, lattice=N
 
 def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=16,
                       ao_radius=15.0, cone_aperture=1.0, build_shadow=False,
-                      light_dir=(0.0, 0.0, 1.0), stream=None):
+                      light_dir=(0.0, 0.0, 1.0), build_rep_lines=False, stream=None):
     lut = _dev(lut, torch.float32)
     d = LodDesc()
     d.lut_rgba = lut.data_ptr()
@@ -241,6 +246,7 @@ def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=1
     d.cone_aperture = cone_aperture
     d.build_shadow = int(build_shadow)
     d.light_dir = (C.c_float * 3)(*light_dir)
+    d.build_rep_lines = int(build_rep_lines)
     _check(lib().lineset_build_lod(ls.handle, C.byref(d), _stream(stream)))
 
 
@@ -258,7 +264,8 @@ def camera_struct(cam) -> CameraS:
 
 def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
-                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False) -> RenderParams:
+                  light_dir=(0.0, 0.0, 1.0), distance_alpha=False, ao_mode=0, shadow_mode=0,
+                  ao_rays=16, ao_radius=15.0, rep_level=1) -> RenderParams:
     p = RenderParams()
     p.radius = radius
     p.mode = mode
@@ -270,6 +277,8 @@ def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_
     p.ka, p.kd, p.ks, p.shininess = ka, kd, ks, shininess
     p.light_dir = (C.c_float * 3)(*light_dir)
     p.distance_alpha = int(distance_alpha)
+    p.ao_mode, p.shadow_mode, p.ao_rays = int(ao_mode), int(shadow_mode), int(ao_rays)
+    p.ao_radius, p.rep_level = float(ao_radius), int(rep_level)
     return p
 
 
@@ -328,7 +337,7 @@ def lineset_pool_stats(device: int = 0) -> dict:
 _EXPORT_DTYPE = {EXPORT_OFFSETS: torch.int32, EXPORT_RECORDS: torch.int64,
                  EXPORT_LOD_COUNT: torch.float32, EXPORT_LOD_LEN: torch.float32,
                  EXPORT_LOD_RHO: torch.float32, EXPORT_AO: torch.float32,
-                 EXPORT_SHADOW: torch.float32}
+                 EXPORT_SHADOW: torch.float32, EXPORT_REP_LINES: torch.int32}
 
 
 def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
@@ -340,7 +349,8 @@ def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
          EXPORT_LOD_COUNT: i.level_off[i.n_levels] if i.n_levels else 0,
          EXPORT_LOD_LEN: i.level_off[i.n_levels] if i.n_levels else 0,
          EXPORT_LOD_RHO: i.level_off[i.n_levels] if i.n_levels else 0,
-         EXPORT_AO: nvox, EXPORT_SHADOW: nvox}[what]
+         EXPORT_AO: nvox, EXPORT_SHADOW: nvox,
+         EXPORT_REP_LINES: i.level_off[i.n_levels] if i.has_rep_lines else 0}[what]
     t = torch.empty(max(int(n), 1), dtype=_EXPORT_DTYPE[what], device="cuda")
     _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
                                 _stream(stream)))

@@ -126,7 +126,7 @@ int ls_alloc(ls_lineset* s, void** p, size_t bytes) {
 
 void ls_free_all(ls_lineset* s) {
   void* ptrs[] = {s->offsets, s->records, s->occupancy, s->lod_count, s->lod_len,
-                  s->lod_rho, s->ao,      s->sh,        s->cone_tab};
+                  s->lod_rho, s->ao,      s->sh,        s->cone_tab, s->rep};
   bool any = false;
   for (void* p : ptrs) any = any || p;
   // work queued on any stream may still read the set (hipFree would wait too)
@@ -139,6 +139,8 @@ void ls_free_all(ls_lineset* s) {
   s->lod_count = s->lod_len = s->lod_rho = s->ao = s->sh = nullptr;
   s->cone_tab = nullptr;
   s->cone_tab_bytes = 0;
+  s->rep = nullptr;
+  s->rep_levels = 0;
   s->bytes = 0;
 }
 
@@ -172,9 +174,34 @@ int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params
     ls_set_error("lineset_render: shading must be 0, 1 or 2");
     return LS_EINVAL;
   }
-  if (p->shading == 2 && (!s->ao || !s->sh)) {
-    ls_set_error("lineset_render: shading 2 needs the AO and shadow grids (lineset_build_lod)");
-    return LS_EINVAL;
+  if (p->shading == 2) {
+    if (p->ao_mode < 0 || p->ao_mode > 1 || p->shadow_mode < 0 || p->shadow_mode > 2) {
+      ls_set_error("lineset_render: ao_mode must be 0 or 1, shadow_mode 0, 1 or 2");
+      return LS_EINVAL;
+    }
+    if ((p->ao_mode == 0 && !s->ao) || (p->shadow_mode == 0 && !s->sh)) {
+      ls_set_error("lineset_render: shading 2 from the per-voxel grids needs them built "
+                   "(lineset_build_lod with build_ao / build_shadow)");
+      return LS_EINVAL;
+    }
+    if ((p->ao_mode == 1 || p->shadow_mode == 1) && !s->lod_rho) {
+      ls_set_error("lineset_render: per-fragment AO or shadow cones need the density pyramid");
+      return LS_EINVAL;
+    }
+    if (p->ao_mode == 1 && (p->ao_rays < 1 || p->ao_rays > 256 || !(p->ao_radius > 0.f) ||
+                            !std::isfinite(p->ao_radius))) {
+      ls_set_error("lineset_render: ao_rays must be in [1, 256] and ao_radius finite and > 0");
+      return LS_EINVAL;
+    }
+    if (p->shadow_mode == 2 && (!s->rep || p->rep_level < 0 || p->rep_level >= s->rep_levels)) {
+      ls_set_error("lineset_render: shadow_mode 2 needs the representative lines "
+                   "(build_rep_lines) and rep_level in [0, levels)");
+      return LS_EINVAL;
+    }
+    if (p->shadow_mode != 0 && !finite3(p->light_dir)) {
+      ls_set_error("lineset_render: non-finite light_dir");
+      return LS_EINVAL;
+    }
   }
   if (!aligned16(out) || !aligned16(p->lut_rgba)) {
     ls_set_error("lineset_render: rgba_out and lut_rgba must be 16-byte aligned");
@@ -338,6 +365,7 @@ int lineset_build_lod(ls_lineset_t s, const ls_lod_desc* d, void* hip_stream) {
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int rc;
   if ((rc = lod_build(s, d->lut_rgba, d->opaque, st))) return rc;
+  if (d->build_rep_lines && (rc = rep_build(s, st))) return rc;
   if (d->build_ao && d->build_shadow) {
     bool applied = false;
     if ((rc = illum_ao_shadow(s, d->ao_cones, d->ao_radius, d->light_dir, d->cone_aperture, st,
@@ -432,6 +460,7 @@ int lineset_info(ls_lineset_t s, ls_info* o) {
   o->n_levels = s->lod_rho ? s->n_levels : 0;
   o->has_ao = s->ao != nullptr;
   o->has_shadow = s->sh != nullptr;
+  o->has_rep_lines = s->rep != nullptr;
   for (int l = 0; l < s->n_levels && l < 32; ++l)
     for (int a = 0; a < 3; ++a) o->level_dims[l][a] = s->level_dims[l][a];
   for (int l = 0; l <= s->n_levels && l < 33; ++l) o->level_off[l] = s->level_off[l];
@@ -457,6 +486,10 @@ int lineset_export(ls_lineset_t s, int32_t what, void* dst, size_t dst_bytes,
     case LS_EXPORT_LOD_RHO: src = s->lod_rho; bytes = lod_bytes; break;
     case LS_EXPORT_AO: src = s->ao; bytes = s->ao ? sizeof(float) * (size_t)s->nvox : 0; break;
     case LS_EXPORT_SHADOW: src = s->sh; bytes = s->sh ? sizeof(float) * (size_t)s->nvox : 0; break;
+    case LS_EXPORT_REP_LINES:
+      src = s->rep;
+      bytes = s->rep ? sizeof(uint32_t) * (size_t)s->level_off[s->rep_levels] : 0;
+      break;
     default:
       ls_set_error("lineset_export: unknown buffer %d", what);
       return LS_EINVAL;

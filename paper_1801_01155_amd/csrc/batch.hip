@@ -18,6 +18,7 @@ struct ls_batch {
   int n_views = 0;
   int total_tiles = 0;
   int32_t flags = 0;
+  bool vdi = false;          // some view uses per-fragment illumination
   BatchPlan plan{2, 2, 0};
   BatchQueues queues{};
   std::vector<ls_view> views;
@@ -41,11 +42,16 @@ constexpr int kQueueWords = 8 + (int)(sizeof(RenderCounters) / sizeof(unsigned))
 std::mutex g_cache_mu;
 std::map<std::string, BatchPlan> g_plan_cache;
 
+bool view_dependent_params(const ls_render_params& p) {
+  return p.shading == 2 && (p.ao_mode != 0 || p.shadow_mode != 0);
+}
+
 std::string signature(const std::vector<ls_view>& v) {
   std::string k;
   for (const auto& x : v) {
     k += std::to_string(x.cam.width) + "x" + std::to_string(x.cam.height) + "m" +
-         std::to_string(x.params.mode) + "o" + std::to_string(x.params.opaque) + ";";
+         std::to_string(x.params.mode) + "o" + std::to_string(x.params.opaque) +
+         (view_dependent_params(x.params) ? "v;" : ";");
   }
   return k;
 }
@@ -96,16 +102,16 @@ int launch(ls_batch* b, bool count, hipStream_t st) {
   int rc;
   if ((rc = fill_u32(b->d_queue, 0u, count ? kQueueWords : 8, st))) return rc;
   return launch_render_batch(b->d_args, b->d_tile_start, b->n_views, b->queues, b->d_queue,
-                             b->plan, count, st);
+                             b->plan, count, b->vdi, st);
 }
 
-int plan_blocks(int wx, int wy, int mult, int* blocks) {
+int plan_blocks(int wx, int wy, int mult, bool vdi, int* blocks) {
   int dev = 0, per_cu = 1;
   LS_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   LS_HIP(hipGetDeviceProperties(&prop, dev));
   int rc;
-  if ((rc = batch_blocks_per_cu(wx, wy, &per_cu))) return rc;
+  if ((rc = batch_blocks_per_cu(wx, wy, vdi, &per_cu))) return rc;
   *blocks = prop.multiProcessorCount * per_cu * mult;
   return LS_OK;
 }
@@ -124,7 +130,7 @@ int autotune(ls_batch* b, hipStream_t st) {
   for (const auto& sh : shapes) {
     for (int mult : mults) {
       BatchPlan p{sh[0], sh[1], 0};
-      if ((rc = plan_blocks(p.wx, p.wy, mult, &p.blocks))) break;
+      if ((rc = plan_blocks(p.wx, p.wy, mult, b->vdi, &p.blocks))) break;
       if ((rc = prepare(b, p, st))) break;
       if ((rc = launch(b, false, st))) break;  // warm
       LS_HIP(hipEventRecord(e0, st));
@@ -241,6 +247,7 @@ int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, v
   b->n_views = n_views;
   b->flags = flags;
   b->views.assign(views, views + n_views);
+  for (const ls_view& x : b->views) b->vdi = b->vdi || view_dependent_params(x.params);
   (void)hipGetDevice(&b->device);
   auto fail = [&](int code) {
     (void)hipStreamSynchronize(st);
@@ -273,7 +280,7 @@ int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, v
     }
   } else {
     BatchPlan p{2, 2, 0};
-    rc = plan_blocks(p.wx, p.wy, 1, &p.blocks);
+    rc = plan_blocks(p.wx, p.wy, 1, b->vdi, &p.blocks);
     if (!rc) rc = prepare(b, p, st);
   }
   if (!rc && (flags & LS_BATCH_GRAPH)) rc = capture(b);
@@ -356,7 +363,9 @@ int lineset_render_batch_static(const ls_view* views, int32_t n_views, void* hip
   RenderArgs args[kStaticViews];
   int32_t tile_start[kStaticViews + 1];
   BatchPlan plan{2, 2, 0};
-  if ((rc = plan_blocks(plan.wx, plan.wy, 1, &plan.blocks))) return rc;
+  bool vdi = false;
+  for (int v = 0; v < n_views; ++v) vdi = vdi || view_dependent_params(views[v].params);
+  if ((rc = plan_blocks(plan.wx, plan.wy, 1, vdi, &plan.blocks))) return rc;
   int64_t total = 0;
   for (int v = 0; v < n_views; ++v) {
     const ls_view& x = views[v];
@@ -379,7 +388,7 @@ int lineset_render_batch_static(const ls_view* views, int32_t n_views, void* hip
   rc = fill_u32(d_queue, 0u, 8, st);
   if (!rc) {
     rc = launch_render_batch(d_args, d_tiles, n_views, make_queues((int)total), d_queue, plan,
-                             false, st);
+                             false, vdi, st);
   }
   // Synchronise on every path from here: the copies read the stack arrays.
   if (hipStreamSynchronize(st) != hipSuccess && !rc) {

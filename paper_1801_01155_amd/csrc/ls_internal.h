@@ -50,6 +50,8 @@ struct ls_lineset {
   float* lod_rho;
   float* ao;
   float* sh;
+  uint32_t* rep;          // representative lines, levels flat at level_off (or null)
+  int32_t rep_levels;
   void* cone_tab;         // plane and tap tables of the column cone tracer
   size_t cone_tab_bytes;
   double lo_scale[4];
@@ -107,6 +109,8 @@ int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream
 int illum_ao_shadow(ls_lineset* s, int n_cones, float radius, const float light[3],
                     float aperture, hipStream_t st, bool* applied);
 int illum_shadow(ls_lineset* s, const float light[3], float aperture, hipStream_t st);
+// Representative lines of every level (replines.hip); allocates s->rep.
+int rep_build(ls_lineset* s, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Rendering (render.hip).

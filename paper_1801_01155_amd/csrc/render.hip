@@ -290,9 +290,202 @@ __device__ inline float fragment_alpha(const RenderArgs& R, float a, float chord
   return 1.f - __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.f - a) * (chord * R.inv_2r));
 }
 
+// ---------------------------------------------------------------------------
+// View-dependent illumination per fragment (sections "Shadow simulation" and
+// "Ambient occlusion"), used by shading 2 when ao_mode / shadow_mode select
+// it. The fragment is the entry point p in the frame of voxel `cell`.
+
+// Dimensions and flat offset of pyramid level lv (each level halves the
+// sides, rounding up, down to 1^3).
+__device__ inline void level_geom(const int32_t g[3], int lv, int32_t dim[3], int64_t& off) {
+  dim[0] = g[0];
+  dim[1] = g[1];
+  dim[2] = g[2];
+  off = 0;
+  for (int l = 0; l < lv; ++l) {
+    off += (int64_t)dim[0] * dim[1] * dim[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dim[a] = (dim[a] + 1) >> 1;
+  }
+}
+
+// Cell-centred trilinear sample, clamped to the edge, of a pyramid level at
+// the point cell + q (finest-voxel units; q may reach far outside the cell).
+__device__ inline float sample_level(const float* lev, const int32_t dim[3], int lv,
+                                     const int32_t cell[3], const float q[3]) {
+  #pragma clang fp contract(fast)
+  const float scale = __builtin_ldexpf(1.0f, -lv);
+  const int32_t mask = (1 << lv) - 1;
+  int32_t i0[3], i1[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = ((float)(cell[a] & mask) + q[a]) * scale - 0.5f;
+    const float fl = floorf(x);
+    f[a] = x - fl;
+    const int32_t lo = (cell[a] >> lv) + (int32_t)fl;
+    i0[a] = min(max(lo, 0), dim[a] - 1);
+    i1[a] = min(max(lo + 1, 0), dim[a] - 1);
+  }
+  const int64_t sy = dim[0], sz = (int64_t)dim[0] * dim[1];
+  const int64_t z0 = i0[2] * sz, z1 = i1[2] * sz, y0 = i0[1] * sy, y1 = i1[1] * sy;
+  const float c00 = lev[i0[0] + y0 + z0] * (1.f - f[0]) + lev[i1[0] + y0 + z0] * f[0];
+  const float c10 = lev[i0[0] + y1 + z0] * (1.f - f[0]) + lev[i1[0] + y1 + z0] * f[0];
+  const float c01 = lev[i0[0] + y0 + z1] * (1.f - f[0]) + lev[i1[0] + y0 + z1] * f[0];
+  const float c11 = lev[i0[0] + y1 + z1] * (1.f - f[0]) + lev[i1[0] + y1 + z1] * f[0];
+  const float c0 = c00 * (1.f - f[1]) + c10 * f[1];
+  const float c1 = c01 * (1.f - f[1]) + c11 * f[1];
+  return c0 * (1.f - f[2]) + c1 * f[2];
+}
+
+__device__ inline bool inside_grid(const RenderArgs& R, const int32_t cell[3], const float q[3]) {
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) in &= q[a] >= -(float)cell[a] && q[a] < (float)(R.g[a] - cell[a]);
+  return in;
+}
+
+// First AO approach: ao_rays rays about the unit normal n, directions of
+// equal area (heights 1 - (i + 0.5)/k) at azimuths i * pi (3 - sqrt 5) in
+// the orthonormal frame of Duff et al. ("Building an Orthonormal Basis,
+// Revisited", JCGT 2017; sign +1 for n_z >= 0). Each ray samples the finest
+// density level at distances s = 1, 2, ... < ao_radius, adding the sample,
+// until the sum reaches 1 or the ray leaves the grid. Returns 1 - mean.
+__device__ inline float hemi_ao(const RenderArgs& R, const int32_t cell[3], const float p[3],
+                                const float n[3]) {
+  #pragma clang fp contract(fast)
+  const float sgn = n[2] >= 0.f ? 1.f : -1.f;
+  const float a = -1.f / (sgn + n[2]);
+  const float b = n[0] * n[1] * a;
+  const float t1[3] = {1.f + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+  const float t2[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+  const int k = R.ao_rays;
+  const float ik = 1.f / (float)k;
+  float sum = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float z = 1.f - ((float)i + 0.5f) * ik;
+    const float r = sqrtf(fmaxf(1.f - z * z, 0.f));
+    // azimuth i * golden angle, reduced in fp64 so large i keeps its accuracy
+    const double ph = (double)i * 2.3999632297286531;
+    const float phr = (float)(ph - 6.283185307179586 * floor(ph * 0.15915494309189535));
+    float sn, cs;
+    sincosf(phr, &sn, &cs);
+    float d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] = r * cs * t1[c] + r * sn * t2[c] + z * n[c];
+    float occ = 0.f;
+    for (float s = 1.f; s < R.ao_radius; s += 1.f) {
+      float q[3] = {p[0] + s * d[0], p[1] + s * d[1], p[2] + s * d[2]};
+      if (!inside_grid(R, cell, q)) break;
+      occ += sample_level(R.rho, R.g, 0, cell, q);
+      if (occ >= 1.f) break;
+    }
+    sum += fminf(occ, 1.f);
+  }
+  return 1.f - sum * ik;
+}
+
+// Second shadow approach at the fragment: a cone of aperture 1 towards the
+// light, samples at s = 1, 2, 4, ... (diameter D = s) on level
+// min(top, log2 s) weighted by D, until the sum reaches 1 or the point leaves
+// the grid. Returns the occlusion (capped at 1).
+__device__ inline float point_cone(const RenderArgs& R, const int32_t cell[3], const float p[3]) {
+  #pragma clang fp contract(fast)
+  int32_t dim[3] = {R.g[0], R.g[1], R.g[2]};
+  int64_t off = 0;
+  int lv = 0;
+  const int top = R.n_levels - 1;
+  float occ = 0.f, s = 1.f;
+  for (int k = 0; k < 64; ++k) {
+    const float q[3] = {p[0] + s * R.light[0], p[1] + s * R.light[1], p[2] + s * R.light[2]};
+    if (!inside_grid(R, cell, q)) break;
+    const int want = min(top, k);
+    while (lv < want) {
+      off += (int64_t)dim[0] * dim[1] * dim[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dim[a] = (dim[a] + 1) >> 1;
+      ++lv;
+    }
+    occ += sample_level(R.rho + off, dim, lv, cell, q) * s;
+    if (occ >= 1.f) break;
+    s += s;
+  }
+  return fminf(occ, 1.f);
+}
+
+// First shadow approach: a ray from the fragment towards the light walks the
+// voxels of level rep_level (the grid walk's fp64 formula, ties to the lowest
+// axis) and tests each voxel's representative line, a capsule of `radius` in
+// that level's voxel units. True when it enters one at a positive distance.
+__device__ inline bool rep_shadow(const RenderArgs& R, const int32_t cell[3], const float p[3]) {
+  const int lv = R.rep_level;
+  int32_t dim[3];
+  int64_t off;
+  level_geom(R.g, lv, dim, off);
+  const uint32_t* rep = R.rep + off;
+  const double scale = ldexp(1.0, -lv);
+  double o[3], d[3], inv[3], tn[3];
+  int32_t c[3], st[3];
+  double tnear = 0.0, tfar = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o[a] = __dmul_rn(__dadd_rn((double)cell[a], (double)p[a]), scale);
+    d[a] = (double)R.light[a];
+    const double iv = __ddiv_rn(1.0, d[a]);
+    if (d[a] != 0.0 && !isinf(iv)) {
+      inv[a] = iv;
+      const double ta = __dmul_rn(__dadd_rn(0.0, -o[a]), iv);
+      const double tb = __dmul_rn(__dadd_rn((double)dim[a], -o[a]), iv);
+      tnear = fmax(tnear, fmin(ta, tb));
+      tfar = fmin(tfar, fmax(ta, tb));
+      st[a] = d[a] > 0.0 ? 1 : -1;
+    } else {
+      inv[a] = 0.0;
+      st[a] = 0;
+      if (!(o[a] >= 0.0 && o[a] < (double)dim[a])) tfar = -INFINITY;
+    }
+  }
+  if (!(tnear < tfar)) return false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double x = __dadd_rn(o[a], __dmul_rn(d[a], tnear));
+    const double fl = floor(x);
+    c[a] = fl < 0.0 ? 0 : (fl > (double)(dim[a] - 1) ? dim[a] - 1 : (int32_t)fl);
+    if (st[a] > 0) tn[a] = __dmul_rn(__dadd_rn((double)(c[a] + 1), -o[a]), inv[a]);
+    else if (st[a] < 0) tn[a] = __dmul_rn(__dadd_rn((double)c[a], -o[a]), inv[a]);
+    else tn[a] = INFINITY;
+  }
+  const float Lf[3] = {R.light[0], R.light[1], R.light[2]};
+  const float dd = dot3(Lf, Lf), inv_dd = 1.f / dd;
+  double t0 = tnear;
+  const int max_steps = dim[0] + dim[1] + dim[2] + 3;
+  for (int it = 0; it < max_steps; ++it) {
+    const uint32_t code = rep[c[0] + (int64_t)dim[0] * (c[1] + (int64_t)dim[1] * c[2])];
+    if (code != 0xFFFFFFFFu) {
+      float a[3], b[3], q[3];
+      decode_point(code & 0x7FFFu, R.inv_bins, a);
+      decode_point((code >> 15) & 0x7FFFu, R.inv_bins, b);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) q[k] = (float)__dadd_rn(__dadd_rn(o[k], __dmul_rn(d[k], t0)), -(double)c[k]);
+      float si, so;
+      if (capsule(q, Lf, dd, inv_dd, a, b, R.r2, si, so) && t0 + (double)si > 0.0) return true;
+    }
+    int ax = 0;
+    if (tn[1] < tn[ax]) ax = 1;
+    if (tn[2] < tn[ax]) ax = 2;
+    t0 = tn[ax];
+    c[ax] += st[ax];
+    if (c[ax] < 0 || c[ax] >= dim[ax]) break;
+    const double plane = (double)(st[ax] > 0 ? c[ax] + 1 : c[ax]);
+    tn[ax] = __dmul_rn(__dadd_rn(plane, -o[ax]), inv[ax]);
+  }
+  return false;
+}
+
 // Shade and composite one fragment. p is the entry point in the frame of
 // `cell`, a/b the record's endpoints in the same frame, dt the ray-parameter
 // length of the hit (exit - entry).
+template <bool kVdi>
 __device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const float4* lut_lds, const Shade& S, Accum& acc, uint64_t rec,
                                  const int32_t cell[3], const float p[3], const float a[3],
                                  const float b[3], float dt, Counts& cnt) {
@@ -320,8 +513,12 @@ __device__ __attribute__((always_inline)) inline void composite(const RenderArgs
 #pragma unroll
       for (int c = 0; c < 3; ++c) col[c] = col[c] * diff + spec;
     } else {
-      float aov = grid_lookup(R.ao, R.g, cell, p);
-      float shv = grid_lookup(R.sh, R.g, cell, p);
+      float aov, shv;
+      if (kVdi && R.ao_mode == 1) aov = hemi_ao(R, cell, p, n);
+      else aov = grid_lookup(R.ao, R.g, cell, p);
+      if (kVdi && R.shadow_mode == 1) shv = 1.f - point_cone(R, cell, p);
+      else if (kVdi && R.shadow_mode == 2) shv = rep_shadow(R, cell, p) ? 0.f : 1.f;
+      else shv = grid_lookup(R.sh, R.g, cell, p);
       float ndl = fmaxf(dot3(n, R.light), 0.f);
       float ndh = fmaxf(dot3(n, S.h), 0.f);
       float spec = R.ks * shv * __builtin_amdgcn_exp2f(R.shin * __builtin_amdgcn_logf(ndh));
@@ -615,6 +812,7 @@ __device__ inline double shfl_f64(double v, int src) {
 
 // Called by all 64 lanes together. Lane `mine` owns the voxel vcell entered
 // at vt0 with lines [lo, hi).
+template <bool kVdi>
 __device__ __attribute__((always_inline)) inline void voxels_coop(
     const RenderArgs& R, const float4* lut_lds, const Ray& ray, const int32_t vcell[3],
     double vt0, const Shade& S, float dd, float inv_dd, bool mine, uint32_t lo, uint32_t hi,
@@ -675,7 +873,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
-        composite(R, lut_lds, S, acc, rec, vcell, p, a, b, 0.f, cnt);
+        composite<kVdi>(R, lut_lds, S, acc, rec, vcell, p, a, b, 0.f, cnt);
         acc.done = true;
       }
     }
@@ -749,7 +947,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rc >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
-        composite(R, lut_lds, S, acc, rc, vcell, p, a, b, t_out - t_in, cnt);
+        composite<kVdi>(R, lut_lds, S, acc, rc, vcell, p, a, b, t_out - t_in, cnt);
       }
       need = more && !acc.done;
       if (need) cnt.passes++;
@@ -844,6 +1042,7 @@ __device__ inline bool capsule_abs(const Ray& ray, double tr, const float q[3], 
   return lo <= hi;
 }
 
+template <bool kVdi>
 __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderArgs& R, const float4* lut_lds, const Ray& ray, const Shade& S, float dd,
                                    float inv_dd, double idd, double t1, Accum& acc, Counts& cnt) {
   double last_t = -INFINITY;
@@ -900,7 +1099,7 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + s_in * ray.d[c];
-      composite(R, lut_lds, S, acc, rec, w, p, a, b, len, cnt);
+      composite<kVdi>(R, lut_lds, S, acc, rec, w, p, a, b, len, cnt);
       if (R.opaque) acc.done = true;
     }
     if (acc.done || !more) break;
@@ -934,7 +1133,7 @@ __device__ inline void flush_counts(RenderCounters* out, const Counts& c) {
   }
 }
 
-template <int kMode>
+template <int kMode, bool kVdi>
 // All 64 lanes of the wave call this together (mode 0 tests lists
 // cooperatively); a lane whose pixel lies outside the image takes part
 // with a dead ray and writes nothing.
@@ -1010,7 +1209,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
             ray.t0 = dda_step(R, ray);
           }
         }
-        voxels_coop(R, lut_lds, ray, vc, vt0, S, dd, inv_dd, mine, lo, hi, acc, cnt);
+        voxels_coop<kVdi>(R, lut_lds, ray, vc, vt0, S, dd, inv_dd, mine, lo, hi, acc, cnt);
       }
     } else {
       for (int it = 0; it < max_steps && ray.alive && !acc.done; ++it) {
@@ -1018,7 +1217,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
         const int64_t vid =
             ray.cell[0] + (int64_t)R.g[0] * (ray.cell[1] + (int64_t)R.g[1] * ray.cell[2]);
         if (R.offsets[vid + 1] > R.offsets[vid]) cnt.nonempty++;
-        voxel_exact(R, lut_lds, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
+        voxel_exact<kVdi>(R, lut_lds, ray, S, dd, inv_dd, idd, peek_t1(ray), acc, cnt);
         ray.t0 = dda_step(R, ray);
       }
     }
@@ -1037,10 +1236,11 @@ __device__ inline void tile_pixel(const RenderArgs& R, int tile, int wave, int l
   j = ty * 8 * R.wy + (wave / R.wx) * 8 + (lane >> 3);
 }
 
+template <bool kVdi>
 __device__ __attribute__((always_inline)) inline void render_any(const RenderArgs& R, const float4* lut_lds, const MergeLds& mt, int i, int j,
                        bool valid, Counts& cnt) {
-  if (R.mode == 0) render_pixel<0>(R, lut_lds, mt, i, j, valid, cnt);
-  else render_pixel<1>(R, lut_lds, mt, i, j, valid, cnt);
+  if (R.mode == 0) render_pixel<0, kVdi>(R, lut_lds, mt, i, j, valid, cnt);
+  else render_pixel<1, kVdi>(R, lut_lds, mt, i, j, valid, cnt);
 }
 
 // Stages a view's transfer function (256 RGBA) in LDS.
@@ -1049,7 +1249,7 @@ __device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
     lut_lds[k] = reinterpret_cast<const float4*>(R.lut)[k];
 }
 
-template <int kMode, bool kCount>
+template <int kMode, bool kCount, bool kVdi>
 __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
   int b = blockIdx.x;
   int tile;
@@ -1132,7 +1332,7 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
     } else {
       tile_pixel(R, tile, threadIdx.x >> 6, lane, i, j);
     }
-    render_pixel<kMode>(R, lut_lds, merge_lds, i, j, valid && i < R.W && j < R.H, cnt);
+    render_pixel<kMode, kVdi>(R, lut_lds, merge_lds, i, j, valid && i < R.W && j < R.H, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
 }
@@ -1142,7 +1342,7 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
 // views' tile counts) is cut into 8 contiguous queues, one per XCD; a
 // workgroup pops tiles from its own XCD's queue and then steals from the
 // others. Every workgroup reaches the exit once all queues are drained.
-template <bool kCount>
+template <bool kCount, bool kVdi>
 __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __restrict__ views,
                                                          const int32_t* __restrict__ tile_start,
                                                          int32_t n_views, BatchQueues q,
@@ -1196,7 +1396,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
     __syncthreads();
     int i, j;
     tile_pixel(R, t - tile_start[v], threadIdx.x >> 6, threadIdx.x & 63, i, j);
-    render_any(R, lut_lds, merge_lds, i, j, i < R.W && j < R.H, cnt);
+    render_any<kVdi>(R, lut_lds, merge_lds, i, j, i < R.W && j < R.H, cnt);
     __syncthreads();
   }
   if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);
@@ -1239,6 +1439,14 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.kd = p->kd;
   R.ks = p->ks;
   R.shin = p->shininess;
+  R.ao_mode = p->shading == 2 ? p->ao_mode : 0;
+  R.shadow_mode = p->shading == 2 ? p->shadow_mode : 0;
+  R.ao_rays = p->ao_rays;
+  R.ao_radius = p->ao_radius;
+  R.rep_level = p->rep_level;
+  R.n_levels = s->lod_rho ? s->n_levels : 0;
+  R.rho = s->lod_rho;
+  R.rep = s->rep;
   R.out = out;
   R.counters = dev_counters;
   R.wx = wx;
@@ -1314,12 +1522,26 @@ int launch_render(const RenderArgs& R, hipStream_t st) {
                       : (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
   const unsigned threads = (unsigned)(64 * R.wx * R.wy);
   const size_t lds = merge_lds_bytes(threads);
+  const dim3 grid(blocks), block(threads);
+  const bool vdi = view_dependent(R), cnt = R.counters != nullptr;
+  // one instance per (mode, counters, view-dependent illumination): the
+  // per-fragment illumination code stays out of the other instances
   if (R.mode == 0) {
-    if (R.counters) hipLaunchKernelGGL((k_render<0, true>), dim3(blocks), dim3(threads), lds, st, R);
-    else hipLaunchKernelGGL((k_render<0, false>), dim3(blocks), dim3(threads), lds, st, R);
+    if (vdi) {
+      if (cnt) hipLaunchKernelGGL((k_render<0, true, true>), grid, block, lds, st, R);
+      else hipLaunchKernelGGL((k_render<0, false, true>), grid, block, lds, st, R);
+    } else {
+      if (cnt) hipLaunchKernelGGL((k_render<0, true, false>), grid, block, lds, st, R);
+      else hipLaunchKernelGGL((k_render<0, false, false>), grid, block, lds, st, R);
+    }
   } else {
-    if (R.counters) hipLaunchKernelGGL((k_render<1, true>), dim3(blocks), dim3(threads), lds, st, R);
-    else hipLaunchKernelGGL((k_render<1, false>), dim3(blocks), dim3(threads), lds, st, R);
+    if (vdi) {
+      if (cnt) hipLaunchKernelGGL((k_render<1, true, true>), grid, block, lds, st, R);
+      else hipLaunchKernelGGL((k_render<1, false, true>), grid, block, lds, st, R);
+    } else {
+      if (cnt) hipLaunchKernelGGL((k_render<1, true, false>), grid, block, lds, st, R);
+      else hipLaunchKernelGGL((k_render<1, false, false>), grid, block, lds, st, R);
+    }
   }
   LS_HIP(hipGetLastError());
   return LS_OK;
@@ -1345,25 +1567,35 @@ BatchQueues make_queues(int total_tiles) {
 
 int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_start, int n_views,
                         const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
-                        bool count, hipStream_t st) {
+                        bool count, bool vdi, hipStream_t st) {
   const unsigned threads = (unsigned)(64 * plan.wx * plan.wy);
   const size_t lds = merge_lds_bytes(threads);
-  if (count)
-    hipLaunchKernelGGL((k_render_batch<true>), dim3(plan.blocks), dim3(threads), lds, st,
-                       dev_views, dev_tile_start, n_views, q, dev_queue);
-  else
-    hipLaunchKernelGGL((k_render_batch<false>), dim3(plan.blocks), dim3(threads), lds, st,
-                       dev_views, dev_tile_start, n_views, q, dev_queue);
+  const dim3 grid(plan.blocks), block(threads);
+  if (vdi) {
+    if (count)
+      hipLaunchKernelGGL((k_render_batch<true, true>), grid, block, lds, st, dev_views,
+                         dev_tile_start, n_views, q, dev_queue);
+    else
+      hipLaunchKernelGGL((k_render_batch<false, true>), grid, block, lds, st, dev_views,
+                         dev_tile_start, n_views, q, dev_queue);
+  } else {
+    if (count)
+      hipLaunchKernelGGL((k_render_batch<true, false>), grid, block, lds, st, dev_views,
+                         dev_tile_start, n_views, q, dev_queue);
+    else
+      hipLaunchKernelGGL((k_render_batch<false, false>), grid, block, lds, st, dev_views,
+                         dev_tile_start, n_views, q, dev_queue);
+  }
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
 int render_merge_slots() { return kMergeSlots; }
 
-int batch_blocks_per_cu(int wx, int wy, int* out) {
+int batch_blocks_per_cu(int wx, int wy, bool vdi, int* out) {
   int n = 0;
-  LS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_render_batch<false>,
-                                                      64 * wx * wy,
+  const void* k = vdi ? (const void*)k_render_batch<false, true> : (const void*)k_render_batch<false, false>;
+  LS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * wx * wy,
                                                       merge_lds_bytes(64u * wx * wy)));
   *out = n > 0 ? n : 1;
   return LS_OK;

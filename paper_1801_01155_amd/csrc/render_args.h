@@ -23,6 +23,12 @@ struct RenderArgs {
   float inv_2r;                   // 1 / (2 radius)
   float ka, kd, ks, shin;
   float light[3];
+  // shading 2 sources: ao_mode 0 grid / 1 hemisphere rays per fragment;
+  // shadow_mode 0 grid / 1 cone per fragment / 2 representative-line ray
+  int32_t ao_mode, shadow_mode, ao_rays, rep_level, n_levels;
+  float ao_radius;
+  const float* rho;               // density pyramid, levels flat
+  const uint32_t* rep;            // representative lines, levels flat
   float* out;
   RenderCounters* counters;
   int32_t wx, wy;                 // tile = wx x wy waves of 8 x 8 pixels
@@ -51,11 +57,17 @@ struct BatchPlan {
 int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
                      float* out, int wx, int wy, RenderCounters* dev_counters, RenderArgs* R);
 int launch_render(const RenderArgs& R, hipStream_t st);
+// True when the view samples the pyramid or the representative lines per
+// fragment (the kernels' view-dependent illumination instance).
+inline bool view_dependent(const RenderArgs& R) {
+  return R.shading == 2 && (R.ao_mode != 0 || R.shadow_mode != 0);
+}
 BatchQueues make_queues(int total_tiles);
 // dev_queue: 8 queue counters (zeroed before the launch), followed by a
 // RenderCounters block when `count` is set.
+// vdi: some view uses view-dependent illumination (view_dependent).
 int launch_render_batch(const RenderArgs* dev_views, const int32_t* dev_tile_start, int n_views,
                         const BatchQueues& q, unsigned* dev_queue, const BatchPlan& plan,
-                        bool count, hipStream_t st);
-int batch_blocks_per_cu(int wx, int wy, int* out);
+                        bool count, bool vdi, hipStream_t st);
+int batch_blocks_per_cu(int wx, int wy, bool vdi, int* out);
 int render_merge_slots();   // intervals in the per-ray curve-merge table

@@ -163,6 +163,8 @@ int launch_slot(ls_server* S, Slot& sl) {
   }
   sl.h_tile_start[n] = (int32_t)total;
   const BatchQueues q = make_queues((int)total);
+  bool vdi = false;
+  for (int k = 0; k < n; ++k) vdi = vdi || view_dependent(sl.h_args[k]);
   // each request's inputs and output were produced on its submitter's stream
   for (Request* r : sl.reqs) LS_HIP(hipStreamWaitEvent(sl.stream, r->ready, 0));
   LS_HIP(hipMemcpyAsync(sl.d_args, sl.h_args, sizeof(RenderArgs) * n, hipMemcpyHostToDevice,
@@ -172,7 +174,7 @@ int launch_slot(ls_server* S, Slot& sl) {
   int rc;
   if ((rc = fill_u32(sl.d_queue, 0u, 8, sl.stream))) return rc;
   if ((rc = launch_render_batch(sl.d_args, sl.d_tile_start, n, q, sl.d_queue, S->plan, false,
-                                sl.stream)))
+                                vdi, sl.stream)))
     return rc;
   LS_HIP(hipEventRecord(sl.done, sl.stream));
   return LS_OK;
@@ -315,7 +317,7 @@ int ls_server_create(const ls_server_config* cfg, ls_server_t* out) {
   int per_cu = 1;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, S->device) != hipSuccess ||
-      batch_blocks_per_cu(2, 2, &per_cu) != LS_OK) {
+      batch_blocks_per_cu(2, 2, false, &per_cu) != LS_OK) {
     delete S;
     ls_set_error("ls_server_create: device query failed");
     return LS_EDEVICE;
