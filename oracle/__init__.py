@@ -37,7 +37,8 @@ _lib = None
 class Csr(C.Structure):
     _fields_ = [("n_records", C.c_int64), ("n_voxels", C.c_int64),
                 ("offsets", C.POINTER(C.c_uint32)), ("records", C.POINTER(C.c_uint64)),
-                ("n_events", C.c_int64), ("n_dropped", C.c_int64)]
+                ("n_events", C.c_int64), ("n_dropped", C.c_int64),
+                ("ends", C.POINTER(C.c_uint16))]
 
 
 class CameraS(C.Structure):
@@ -55,7 +56,7 @@ class ParamsS(C.Structure):
                 ("distance_alpha", C.c_int32), ("ao_mode", C.c_int32),
                 ("shadow_mode", C.c_int32), ("ao_rays", C.c_int32), ("ao_radius", C.c_float),
                 ("rep_level", C.c_int32), ("rho", C.POINTER(C.c_double)),
-                ("rep", C.POINTER(C.c_uint32))]
+                ("rep", C.POINTER(C.c_uint32)), ("ends", C.POINTER(C.c_uint16))]
 
 
 class CountersS(C.Structure):
@@ -126,9 +127,13 @@ class OracleCsr:
     records: np.ndarray   # uint64 [S]
     n_events: int
     n_dropped: int
+    ends: np.ndarray = None   # uint16 [S] endpoint attributes (per-vertex input), or None
 
 
-def voxelize(lattice: np.ndarray, curve_off: np.ndarray, attr, grid, bins: int) -> OracleCsr:
+def voxelize(lattice: np.ndarray, curve_off: np.ndarray, attr, grid, bins: int,
+             vattr=None) -> OracleCsr:
+    """vattr: optional per-vertex attribute bytes (interpolated to the lines'
+    endpoints; the records' attribute byte is then their mean)."""
     lat = np.ascontiguousarray(lattice, dtype=np.int32).reshape(-1, 3)
     off = np.ascontiguousarray(curve_off, dtype=np.int64)
     g = _grid(grid)
@@ -137,9 +142,16 @@ def voxelize(lattice: np.ndarray, curve_off: np.ndarray, attr, grid, bins: int) 
     if attr is not None:
         attr = np.ascontiguousarray(attr, dtype=np.uint8)
         ap = _p(attr, C.c_uint8)
+    vp = None
+    if vattr is not None:
+        vattr = np.ascontiguousarray(vattr, dtype=np.uint8)
+        if vattr.shape[0] != lat.shape[0]:
+            raise ValueError("vattr needs one byte per vertex")
+        vp = _p(vattr, C.c_uint8)
     out = Csr()
-    rc = lib().or_voxelize(_p(lat, C.c_int32), _p(off, C.c_int64), ap, C.c_int64(n_curves),
-                           _p(g, C.c_int32), C.c_int32(bins), C.byref(out))
+    rc = lib().or_voxelize_attr(_p(lat, C.c_int32), _p(off, C.c_int64), ap, vp,
+                                C.c_int64(n_curves), _p(g, C.c_int32), C.c_int32(bins),
+                                C.byref(out))
     if rc != 0:
         raise ValueError("or_voxelize failed (%d)" % rc)
     try:
@@ -148,7 +160,11 @@ def voxelize(lattice: np.ndarray, curve_off: np.ndarray, attr, grid, bins: int) 
         n = int(out.n_records)
         recs = (np.ctypeslib.as_array(out.records, shape=(n,)).copy() if n > 0
                 else np.zeros(0, dtype=np.uint64))
-        return OracleCsr(offs, recs, int(out.n_events), int(out.n_dropped))
+        ends = None
+        if vattr is not None:
+            ends = (np.ctypeslib.as_array(out.ends, shape=(n,)).copy() if n > 0
+                    else np.zeros(0, dtype=np.uint16))
+        return OracleCsr(offs, recs, int(out.n_events), int(out.n_dropped), ends)
     finally:
         lib().or_csr_free(C.byref(out))
 
@@ -202,6 +218,29 @@ def ao_grid(rho, grid, n_cones=16, radius=15.0, aperture=1.0, threads=0):
     lib().or_ao_grid(_p(rho, C.c_double), _p(g, C.c_int32), n_cones, radius, aperture,
                      _p(ao, C.c_double), threads)
     return ao
+
+
+def ao_grid_part(rho, grid, v0, v1, n_cones=16, radius=15.0, aperture=1.0, threads=0):
+    """AO of voxels [v0, v1) only (a bounded sample of ao_grid)."""
+    g = _grid(grid)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    ao = np.zeros(int(v1 - v0))
+    lib().or_ao_grid_part(_p(rho, C.c_double), _p(g, C.c_int32), C.c_int32(n_cones),
+                          C.c_double(radius), C.c_double(aperture), C.c_int64(v0), C.c_int64(v1),
+                          _p(ao, C.c_double), C.c_int32(threads))
+    return ao
+
+
+def shadow_grid_part(rho, grid, light, v0, v1, aperture=1.0, threads=0):
+    """Shadow factors of voxels [v0, v1) only."""
+    g = _grid(grid)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    L = np.ascontiguousarray(light, dtype=np.float64)
+    sh = np.zeros(int(v1 - v0))
+    lib().or_shadow_grid_part(_p(rho, C.c_double), _p(g, C.c_int32), _p(L, C.c_double),
+                              C.c_double(aperture), C.c_int64(v0), C.c_int64(v1),
+                              _p(sh, C.c_double), C.c_int32(threads))
+    return sh
 
 
 def shadow_grid(rho, grid, light, aperture=1.0, threads=0):
@@ -341,6 +380,10 @@ def render(csr: OracleCsr, grid, bins: int, cam, pixels=None, ao=None, sh=None,
     if rep is not None:
         rep = np.ascontiguousarray(rep, dtype=np.uint32)
         p.rep = _p(rep, C.c_uint32)
+    ends = getattr(csr, "ends", None)
+    if ends is not None:
+        ends = np.ascontiguousarray(ends, dtype=np.uint16)
+        p.ends = _p(ends, C.c_uint16)
     if pixels is not None:
         pix = np.ascontiguousarray(pixels, dtype=np.int64)
         n = pix.shape[0]

@@ -83,7 +83,17 @@ typedef struct {
   int64_t xn[3];   /* event point * den, exact */
   int64_t den;
   uint32_t entry_code, exit_code;
+  uint32_t attr;   /* vertex attribute interpolated to the event point */
 } or_event;
+
+/* Section "Curve voxelization": line attributes interpolated to the
+ * line-face intersection points. The event lies at t = num / den along the
+ * segment whose vertices carry a0 and a1; its attribute is a0 + (a1 - a0) t
+ * rounded to the nearest integer (halves up), in exact integer arithmetic. */
+static uint32_t event_attr(uint32_t a0, uint32_t a1, int64_t num, int64_t den) {
+  int64_t s = 2 * ((int64_t)a0 * den + ((int64_t)a1 - (int64_t)a0) * num) + den;
+  return (uint32_t)(s / (2 * den));
+}
 
 static uint32_t face_code(int axis, int side, const int64_t xn[3], int64_t den,
                           const int32_t cell[3], int32_t bins) {
@@ -102,10 +112,11 @@ static uint32_t face_code(int axis, int side, const int64_t xn[3], int64_t den,
 typedef struct {
   uint32_t* vox;
   uint64_t* rec;
+  uint16_t* ends;
   int64_t n, cap;
 } rec_buf;
 
-static int push_rec(rec_buf* b, uint32_t vox, uint64_t rec) {
+static int push_rec(rec_buf* b, uint32_t vox, uint64_t rec, uint16_t ends) {
   if (b->n == b->cap) {
     int64_t nc = b->cap ? 2 * b->cap : 1024;
     uint32_t* v2 = (uint32_t*)realloc(b->vox, (size_t)nc * sizeof(uint32_t));
@@ -114,16 +125,30 @@ static int push_rec(rec_buf* b, uint32_t vox, uint64_t rec) {
     uint64_t* r2 = (uint64_t*)realloc(b->rec, (size_t)nc * sizeof(uint64_t));
     if (!r2) return -1;
     b->rec = r2;
+    uint16_t* e2 = (uint16_t*)realloc(b->ends, (size_t)nc * sizeof(uint16_t));
+    if (!e2) return -1;
+    b->ends = e2;
     b->cap = nc;
   }
   b->vox[b->n] = vox;
   b->rec[b->n] = rec;
+  b->ends[b->n] = ends;
   b->n++;
   return 0;
 }
 
 int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* attr,
                 int64_t n_curves, const int32_t grid[3], int32_t bins, or_csr* out) {
+  return or_voxelize_attr(lat, curve_off, attr, NULL, n_curves, grid, bins, out);
+}
+
+/* With per-vertex attributes (vattr, one byte per vertex), every event gets
+ * the attribute interpolated to its point, each line keeps the attributes of
+ * its two endpoints (out->ends: entry | exit << 8, in CSR order), and the
+ * record's attribute byte is their mean rounded down, (entry + exit) / 2. */
+int or_voxelize_attr(const int32_t* lat, const int64_t* curve_off, const uint8_t* attr,
+                     const uint8_t* vattr, int64_t n_curves, const int32_t grid[3], int32_t bins,
+                     or_csr* out) {
   memset(out, 0, sizeof(*out));
   for (int a = 0; a < 3; ++a)
     if (grid[a] < 1 || grid[a] > MAX_DIM) return -1;
@@ -189,6 +214,7 @@ int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* att
         int exit_side = sgn[fa] > 0 ? 1 : 0;
         ev.exit_code = face_code(fa, exit_side, ev.xn, ev.den, cell, bins);
         ev.entry_code = face_code(fa, 1 - exit_side, ev.xn, ev.den, ncell, bins);
+        ev.attr = vattr ? event_attr(vattr[i], vattr[i + 1], num, ev.den) : 0;
         n_events++;
         if (have_prev) {
           /* the line inside `cell` runs from prev's entry to this exit */
@@ -200,7 +226,12 @@ int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* att
           } else {
             uint32_t vox = (uint32_t)(cell[0] + (int64_t)grid[0] * (cell[1] + (int64_t)grid[1] * cell[2]));
             uint64_t rec = (uint64_t)prev.entry_code | ((uint64_t)ev.exit_code << 15) | hi_bits;
-            if (push_rec(&buf, vox, rec)) goto oom;
+            uint16_t ends = 0;
+            if (vattr) {
+              rec = (rec & ~((uint64_t)0xFF << 32)) | ((uint64_t)((prev.attr + ev.attr) / 2) << 32);
+              ends = (uint16_t)(prev.attr | (ev.attr << 8));
+            }
+            if (push_rec(&buf, vox, rec, ends)) goto oom;
           }
         }
         prev = ev;
@@ -222,6 +253,10 @@ int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* att
   out->offsets = (uint32_t*)calloc((size_t)nvox + 1, sizeof(uint32_t));
   out->records = (uint64_t*)malloc((size_t)(buf.n > 0 ? buf.n : 1) * sizeof(uint64_t));
   if (!out->offsets || !out->records) goto oom;
+  if (vattr) {
+    out->ends = (uint16_t*)malloc((size_t)(buf.n > 0 ? buf.n : 1) * sizeof(uint16_t));
+    if (!out->ends) goto oom;
+  }
   if (buf.n > 0xFFFFFFFFll) goto oom;
   for (int64_t r = 0; r < buf.n; ++r) out->offsets[buf.vox[r] + 1]++;
   for (int64_t v = 0; v < nvox; ++v) out->offsets[v + 1] += out->offsets[v];
@@ -229,15 +264,21 @@ int or_voxelize(const int32_t* lat, const int64_t* curve_off, const uint8_t* att
     uint32_t* cursor = (uint32_t*)malloc((size_t)(nvox > 0 ? nvox : 1) * sizeof(uint32_t));
     if (!cursor) goto oom;
     memcpy(cursor, out->offsets, (size_t)nvox * sizeof(uint32_t));
-    for (int64_t r = 0; r < buf.n; ++r) out->records[cursor[buf.vox[r]]++] = buf.rec[r];
+    for (int64_t r = 0; r < buf.n; ++r) {
+      uint32_t at = cursor[buf.vox[r]]++;
+      out->records[at] = buf.rec[r];
+      if (vattr) out->ends[at] = buf.ends[r];
+    }
     free(cursor);
   }
   free(buf.vox);
   free(buf.rec);
+  free(buf.ends);
   return 0;
 oom:
   free(buf.vox);
   free(buf.rec);
+  free(buf.ends);
   or_csr_free(out);
   return -2;
 }
@@ -245,8 +286,10 @@ oom:
 void or_csr_free(or_csr* c) {
   free(c->offsets);
   free(c->records);
+  free(c->ends);
   c->offsets = NULL;
   c->records = NULL;
+  c->ends = NULL;
 }
 
 int or_paper_record_bytes(int32_t bins) {
@@ -422,20 +465,26 @@ void or_fibonacci_dirs(int32_t n, double* dirs) {
 
 int or_ao_grid(const double* rho, const int32_t grid[3], int32_t n_cones,
                double radius, double aperture, double* ao, int32_t n_threads) {
+  return or_ao_grid_part(rho, grid, n_cones, radius, aperture, 0,
+                         (int64_t)grid[0] * grid[1] * grid[2], ao, n_threads);
+}
+
+/* Voxels [v0, v1) of the AO grid into ao[v - v0]. */
+int or_ao_grid_part(const double* rho, const int32_t grid[3], int32_t n_cones, double radius,
+                    double aperture, int64_t v0, int64_t v1, double* ao, int32_t n_threads) {
   double* dirs = (double*)malloc((size_t)n_cones * 3 * sizeof(double));
   if (!dirs) return -2;
   or_fibonacci_dirs(n_cones, dirs);
-  int64_t nvox = (int64_t)grid[0] * grid[1] * grid[2];
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 256)
 #endif
-  for (int64_t v = 0; v < nvox; ++v) {
+  for (int64_t v = v0; v < v1; ++v) {
     int64_t x = v % grid[0], y = (v / grid[0]) % grid[1], z = v / ((int64_t)grid[0] * grid[1]);
     double p[3] = {x + 0.5, y + 0.5, z + 0.5};
     double sum = 0;
     for (int32_t c = 0; c < n_cones; ++c) sum += or_cone(rho, grid, p, dirs + 3 * c, radius, aperture);
-    ao[v] = 1.0 - sum / (double)n_cones;
+    ao[v - v0] = 1.0 - sum / (double)n_cones;
   }
   free(dirs);
   return 0;
@@ -443,15 +492,21 @@ int or_ao_grid(const double* rho, const int32_t grid[3], int32_t n_cones,
 
 int or_shadow_grid(const double* rho, const int32_t grid[3], const double light[3],
                    double aperture, double* sh, int32_t n_threads) {
-  int64_t nvox = (int64_t)grid[0] * grid[1] * grid[2];
+  return or_shadow_grid_part(rho, grid, light, aperture, 0,
+                             (int64_t)grid[0] * grid[1] * grid[2], sh, n_threads);
+}
+
+/* Voxels [v0, v1) of the shadow grid into sh[v - v0]. */
+int or_shadow_grid_part(const double* rho, const int32_t grid[3], const double light[3],
+                        double aperture, int64_t v0, int64_t v1, double* sh, int32_t n_threads) {
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 256)
 #endif
-  for (int64_t v = 0; v < nvox; ++v) {
+  for (int64_t v = v0; v < v1; ++v) {
     int64_t x = v % grid[0], y = (v / grid[0]) % grid[1], z = v / ((int64_t)grid[0] * grid[1]);
     double p[3] = {x + 0.5, y + 0.5, z + 0.5};
-    sh[v] = 1.0 - or_cone(rho, grid, p, light, INFINITY, aperture);
+    sh[v - v0] = 1.0 - or_cone(rho, grid, p, light, INFINITY, aperture);
   }
   return 0;
 }
@@ -941,6 +996,7 @@ typedef struct {
   uint32_t idx;
   double n[3];
   double x[3];
+  int32_t cell[3];   /* the voxel owning the line */
 } or_hit;
 
 static int cmp_hit(const void* pa, const void* pb) {
@@ -991,7 +1047,7 @@ static void test_list(const rctx* c, int64_t vox, const int32_t cell[3], const d
     h->t_in = ti;
     h->t_out = to;
     h->idx = r;
-    for (int q = 0; q < 3; ++q) { h->n[q] = n[q]; h->x[q] = o[q] + ti * d[q]; }
+    for (int q = 0; q < 3; ++q) { h->n[q] = n[q]; h->x[q] = o[q] + ti * d[q]; h->cell[q] = cell[q]; }
   }
 }
 
@@ -1065,6 +1121,31 @@ static void render_pixel(const rctx* c, int32_t i, int32_t j, double out[4], or_
       const float* lut = p->lut_rgba + 4 * attr;
       double base[3] = {lut[0], lut[1], lut[2]};
       double alpha = p->opaque ? 1.0 : (double)lut[3];
+      if (p->ends) {
+        /* Attributes interpolated along the line: the endpoint attributes
+         * taken linearly at the segment point closest to the entry point
+         * (clamped to the segment), and the transfer function read linearly
+         * between its two neighbouring entries. */
+        double ea[3], eb[3], A[3], B[3];
+        or_decode(rec, c->bins, ea, eb);
+        for (int q = 0; q < 3; ++q) { A[q] = H->cell[q] + ea[q]; B[q] = H->cell[q] + eb[q]; }
+        double ba[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        double pa[3] = {H->x[0] - A[0], H->x[1] - A[1], H->x[2] - A[2]};
+        double u = dot3(pa, ba) / dot3(ba, ba);
+        if (u < 0) u = 0;
+        if (u > 1) u = 1;
+        uint16_t en = p->ends[H->idx];
+        double a0 = (double)(en & 0xFF), a1 = (double)(en >> 8);
+        double af = a0 + u * (a1 - a0);
+        int i0 = (int)floor(af);
+        if (i0 > 255) i0 = 255;
+        int i1 = i0 < 255 ? i0 + 1 : 255;
+        double f = af - (double)i0;
+        const float* l0 = p->lut_rgba + 4 * i0;
+        const float* l1 = p->lut_rgba + 4 * i1;
+        for (int q = 0; q < 3; ++q) base[q] = (1.0 - f) * (double)l0[q] + f * (double)l1[q];
+        if (!p->opaque) alpha = (1.0 - f) * (double)l0[3] + f * (double)l1[3];
+      }
       if (!p->opaque && p->distance_alpha) {
         /* Section "Transparency rendering": opacity dependent on the distance
          * travelled inside the tube. Reading: the transfer function's alpha

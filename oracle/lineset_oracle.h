@@ -39,12 +39,20 @@ typedef struct {
   uint64_t* records;   /* [n_records] */
   int64_t n_events;
   int64_t n_dropped;
+  uint16_t* ends;      /* [n_records] endpoint attributes entry | exit << 8, or NULL */
 } or_csr;
 
 /* Sections "Curve voxelization", "Line quantization", "GPU implementation". */
 int or_voxelize(const int32_t* lattice, const int64_t* curve_off,
                 const uint8_t* attr, int64_t n_curves, const int32_t grid[3],
                 int32_t bins, or_csr* out);
+/* The same with per-vertex attributes (section "Curve voxelization": line
+ * attributes interpolated to the line-face intersection points): vattr holds
+ * one byte per vertex (NULL: none); out->ends gets each line's endpoint
+ * attributes and its record's attribute byte their mean (rounded down). */
+int or_voxelize_attr(const int32_t* lat, const int64_t* curve_off, const uint8_t* attr,
+                     const uint8_t* vattr, int64_t n_curves, const int32_t grid[3], int32_t bins,
+                     or_csr* out);
 void or_csr_free(or_csr* c);
 
 /* Section "Memory statistics": bytes per quantized line in the paper's
@@ -69,6 +77,11 @@ int or_ao_grid(const double* rho, const int32_t grid[3], int32_t n_cones,
                double radius, double aperture, double* ao, int32_t n_threads);
 int or_shadow_grid(const double* rho, const int32_t grid[3], const double light[3],
                    double aperture, double* sh, int32_t n_threads);
+/* The same grids over voxels [v0, v1) only (out[v - v0]): bounded samples. */
+int or_ao_grid_part(const double* rho, const int32_t grid[3], int32_t n_cones, double radius,
+                    double aperture, int64_t v0, int64_t v1, double* ao, int32_t n_threads);
+int or_shadow_grid_part(const double* rho, const int32_t grid[3], const double light[3],
+                        double aperture, int64_t v0, int64_t v1, double* sh, int32_t n_threads);
 
 /* Section "LoD construction": one representative line per voxel and level
  * (code = record bits 0..29, 0xFFFFFFFF for none), levels flat at the
@@ -113,6 +126,8 @@ typedef struct {
   int32_t rep_level;     /* level of the representative lines (shadow_mode 2) */
   const double* rho;     /* density pyramid, levels flat (ao_mode 1, shadow_mode 1) */
   const uint32_t* rep;   /* representative lines, levels flat (shadow_mode 2) */
+  const uint16_t* ends;  /* per-record endpoint attributes (or NULL): colour and
+                            opacity from the attribute interpolated along the line */
 } or_params;
 
 typedef struct {

@@ -30,9 +30,12 @@ def _code(face, bu, bw):
     return face | (bu << 3) | (bw << 9)
 
 
-def curve_records(verts, bins):
+def curve_records(verts, bins, vattr=None):
     """verts: list of integer (x, y, z) lattice points. Returns a list of
-    (voxel_cell, entry_code, exit_code) in order along the curve."""
+    (voxel_cell, entry_code, exit_code) in order along the curve; with
+    per-vertex attributes vattr, (voxel_cell, entry_code, exit_code,
+    entry_attr, exit_attr), an event's attribute being a_i + (a_{i+1} - a_i) t
+    rounded half up (t the exact parameter of the event on its segment)."""
     if len(verts) < 2:
         return []
     events = []  # (point (Fractions), exit_code_old_cell, entry_code_new_cell, old, new)
@@ -65,36 +68,50 @@ def curve_records(verts, bins):
             entry_face = 2 * fa + (0 if up else 1)
             ex = _code(exit_face, *_face_bins(fa, point, cell, bins))
             en = _code(entry_face, *_face_bins(fa, point, new, bins))
-            events.append((point, ex, en, cell, new))
+            at = None
+            if vattr is not None:
+                at = floor(vattr[i] + t * (vattr[i + 1] - vattr[i]) + Fraction(1, 2))
+            events.append((point, ex, en, cell, new, at))
             cell = new
     assert cell == tuple(v // 256 for v in verts[-1])
     recs = []
     for j in range(len(events) - 1):
-        p0, _, entry, _, c_in = events[j]
-        p1, exit_, _, c_out, _ = events[j + 1]
+        p0, _, entry, _, c_in, a_in = events[j]
+        p1, exit_, _, c_out, _, a_out = events[j + 1]
         assert c_in == c_out
         if p0 == p1 or entry == exit_:
             continue
-        recs.append((c_in, entry, exit_))
+        recs.append((c_in, entry, exit_) if vattr is None else (c_in, entry, exit_, a_in, a_out))
     return recs
 
 
-def voxelize(lattice, curve_off, attr, grid, bins):
-    """Returns (offsets list, records list) in the oracle's CSR format."""
+def voxelize(lattice, curve_off, attr, grid, bins, vattr=None):
+    """Returns (offsets list, records list) in the oracle's CSR format; with
+    per-vertex attributes also the per-record endpoint attributes
+    (entry | exit << 8) and the records' attribute byte their mean."""
     gx, gy, gz = grid
     items = []
     for c in range(len(curve_off) - 1):
         verts = [tuple(int(x) for x in lattice[v]) for v in range(curve_off[c], curve_off[c + 1])]
+        va = None if vattr is None else [int(vattr[v]) for v in range(curve_off[c], curve_off[c + 1])]
         a = 255 if attr is None else int(attr[c])
-        for (cx, cy, cz), entry, exit_ in curve_records(verts, bins):
+        for r in curve_records(verts, bins, va):
+            (cx, cy, cz), entry, exit_ = r[:3]
+            ends = 0
+            aa = a
+            if va is not None:
+                aa = (r[3] + r[4]) // 2
+                ends = r[3] | (r[4] << 8)
             vox = cx + gx * (cy + gy * cz)
-            rec = entry | (exit_ << 15) | (a << 32) | ((c & 0xFFFFFF) << 40)
-            items.append((vox, len(items), rec))
+            rec = entry | (exit_ << 15) | (aa << 32) | ((c & 0xFFFFFF) << 40)
+            items.append((vox, len(items), rec, ends))
     items.sort()
     nvox = gx * gy * gz
     counts = [0] * (nvox + 1)
-    for vox, _, _ in items:
-        counts[vox + 1] += 1
+    for it in items:
+        counts[it[0] + 1] += 1
     for v in range(nvox):
         counts[v + 1] += counts[v]
-    return counts, [r for _, _, r in items]
+    if vattr is None:
+        return counts, [it[2] for it in items]
+    return counts, [it[2] for it in items], [it[3] for it in items]

@@ -137,3 +137,25 @@ def test_ao_grid_on_workload_in_range():
     sh = O.shadow_grid(rho, 32, synth.LIGHT_DIR, threads=4)
     assert (ao >= 0).all() and (ao <= 1).all() and ao.min() < 0.99
     assert (sh >= 0).all() and (sh <= 1).all() and sh.min() < 0.99
+
+
+def test_grid_parts_equal_full_grids():
+    """The voxel-range variants (bounded CPU-baseline samples) compute the
+    same values as the full AO and shadow grids."""
+    rng = np.random.default_rng(12)
+    g = (12, 10, 9)
+    dims, loff = O.lod_levels(g)
+    rho = np.zeros(int(loff[-1]))
+    rho[:loff[1]] = rng.random(int(loff[1])) * 0.2
+    for lv in range(1, len(dims)):
+        prev = rho[loff[lv - 1]:loff[lv]].reshape(dims[lv - 1][::-1])
+        d = dims[lv]
+        pad = np.zeros((2 * d[2], 2 * d[1], 2 * d[0]))
+        pad[:prev.shape[0], :prev.shape[1], :prev.shape[2]] = prev
+        rho[loff[lv]:loff[lv + 1]] = pad.reshape(d[2], 2, d[1], 2, d[0], 2).mean(axis=(1, 3, 5)).ravel()
+    ao = O.ao_grid(rho, g, 16, 15.0, 1.0)
+    L = (0.3, -0.4, 0.866)
+    sh = O.shadow_grid(rho, g, L)
+    for v0, v1 in ((0, 100), (317, 900), (0, ao.size)):
+        assert np.array_equal(O.ao_grid_part(rho, g, v0, v1, 16, 15.0, 1.0), ao[v0:v1])
+        assert np.array_equal(O.shadow_grid_part(rho, g, L, v0, v1), sh[v0:v1])
