@@ -33,9 +33,20 @@ COPY_CAL_BYTES = 2 << 30
 # counted bytes). The figure holds for the kernel source it was measured on
 # only: bench reports it when csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
-    "render_hip_sha256": "1cb7bf0c76ba99178c17802c32f590a4cf6a4cdb417cf8d981c73f0dffb656ce",
-    "bytes_per_launch": 114096190,
+    "render_hip_sha256": "02f9ae8849f4b9c84f66cb19bffe98a3d87fca44b4fb0f359f6ba98fc1f6cce1",
+    "bytes_per_launch": 114202958,
 }
+# Counters of the same launch and source, from one rocprofv3 --pmc run
+# (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU
+# SQ_THREAD_CYCLES_VALU TCC_HIT_sum TCC_MISS_sum): L2 hit = hits / (hits +
+# misses); VALU lane use = thread-cycles / (64 x wave instructions); waits =
+# SQ_WAIT_ANY / SQ_WAVE_CYCLES.
+RENDER_COUNTERS = {"l2_hit": 0.820, "valu_lane_use": 0.346, "wait_frac": 0.340}
+# fp32 operations of one ray-capsule test (two sphere quadratics, the
+# projected cylinder quadratic and its slab clip), counted from the kernel
+# source; the VALU figure of the roofline is tests x this / launch time.
+CAPSULE_FLOPS = 100
+VALU_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -55,6 +66,10 @@ def parse():
                     help="oracle renders every k-th image row")
     ap.add_argument("--no-update", action="store_true",
                     help="skip the incremental-update leg")
+    ap.add_argument("--no-gi", action="store_true",
+                    help="skip the global-illumination (512^3) leg")
+    ap.add_argument("--no-vdi", action="store_true",
+                    help="skip the view-dependent illumination leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the open-loop serving sweep")
     ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
@@ -70,22 +85,63 @@ def parse():
     return ap.parse_args()
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_1thread(w, cam, lut, light, csr, rho, t_vox):
+    """The same step on one host thread: the voxelizer (single-threaded, timed
+    in full by the caller) and the pyramid in full, AO + shadow for 4
+    z-planes of voxels, render every 64th row; samples scaled to the step."""
+    import oracle as O
+    grid, bins = w["grid"], w["bins"]
+    t = time.perf_counter()
+    O.lod(csr, grid, bins, lut, opaque=w["opaque"])
+    t_lod = time.perf_counter() - t
+    G2 = grid * grid
+    v0, v1 = (grid // 2) * G2, (grid // 2 + 4) * G2
+    L64 = np.array(light, np.float32).astype(np.float64)
+    t = time.perf_counter()
+    O.ao_grid_part(rho, grid, v0, v1, 16, 15.0, 1.0, threads=1)
+    O.shadow_grid_part(rho, grid, L64, v0, v1, threads=1)
+    t_illum = t_lod + (time.perf_counter() - t) * (grid ** 3 / (v1 - v0))
+    W, H = cam.width, cam.height
+    rows = np.arange(0, H, 64)
+    pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel()
+    ao = np.full(grid ** 3, 0.5)
+    sh = np.full(grid ** 3, 0.5)
+    t = time.perf_counter()
+    O.render(csr, grid, bins, cam, pixels=pix, ao=ao, sh=sh, threads=1, lut=lut,
+             radius=w["radius"], opaque=w["opaque"], shading=2, light_dir=light)
+    t_render = (time.perf_counter() - t) * (W * H / len(pix))
+    step = t_vox + t_illum + t_render
+    return {"value": W * H / step / 1e6, "unit": "Mrays/s", "cores": 1,
+            "sample": (f"voxelize in full; LoD full; AO+shadow for {v1 - v0} voxels "
+                       f"(x{grid ** 3 / (v1 - v0):.0f}); render {len(pix)} pixels (every 64th "
+                       f"row); per-step s: vox {t_vox:.2f} illum {t_illum:.2f} "
+                       f"render {t_render:.2f}")}
+
+
 def cpu_baseline(ls, w, cam, lut, light, row_stride):
-    """The oracle, untuned, on the host cores: voxelize a 10% curve sample,
-    LoD + AO + shadow grids in full, render every row_stride-th row; scaled
-    to one full step."""
+    """The oracle, untuned, on the host cores: grid set-up and voxelization in
+    full (single-threaded code), LoD + AO + shadow grids in full, render every
+    row_stride-th row (scaled to the frame). Also the same step on one thread
+    (smaller AO/shadow and render samples)."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     grid, bins = w["grid"], w["bins"]
-    sub = max(1, ls.n_curves // 10)
-    off = ls.curve_off[:sub + 1]
     t = time.perf_counter()
-    lat, _, _ = O.grid_setup(ls.xyz[:off[-1]], grid)
-    O.voxelize(lat, off, ls.attr[:sub], grid, bins)
-    t_vox = (time.perf_counter() - t) * (ls.n_curves / sub)
-    # full CSR for the later stages (not timed)
     lat, _, _ = O.grid_setup(ls.xyz, grid)
     csr = O.voxelize(lat, ls.curve_off, ls.attr, grid, bins)
+    t_vox = time.perf_counter() - t
+    del lat
     t = time.perf_counter()
     _, _, rho, _, _ = O.lod(csr, grid, bins, lut, opaque=w["opaque"])
     ao = O.ao_grid(rho, grid, 16, 15.0, 1.0, threads=threads)
@@ -99,12 +155,15 @@ def cpu_baseline(ls, w, cam, lut, light, row_stride):
              radius=w["radius"], opaque=w["opaque"], shading=2, light_dir=light)
     t_render = (time.perf_counter() - t) * (W * H / len(pix))
     step = t_vox + t_illum + t_render
+    one = cpu_baseline_1thread(w, cam, lut, light, csr, rho, t_vox)
     return {
         "value": W * H / step / 1e6,
         "unit": "Mrays/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"voxelize {sub} of {ls.n_curves} curves (x{ls.n_curves / sub:.0f}); "
+        "cpu_model": _cpu_model(),
+        "one_thread": one,
+        "sample": (f"grid set-up + voxelize all {ls.n_curves} curves; "
                    f"LoD+AO+shadow grids full; render {len(pix)} of {W * H} pixels "
                    f"(every {row_stride}th row); per-step s: vox {t_vox:.2f} "
                    f"illum {t_illum:.2f} render {t_render:.2f}"),
@@ -250,6 +309,119 @@ def update_leg(L, synth, torch, dev, stream, ls, w, reps=5, frac=0.01):
     return res
 
 
+def gi_leg(L, synth, torch, dev, stream, reps=3):
+    """The global-illumination workload (1M ABC-flow streamlines x 100
+    vertices, perturbed; 512^3 grid, 32^2 bins; transparent; 16-cone AO and a
+    soft shadow; 1920x1080 with AO/shadow shading): the same step as the main
+    line (voxelize -> pyramid + AO + shadow grids -> render), timed per phase
+    with events on the launch stream, and the ray caster's algorithmic bytes
+    per launch."""
+    w = dict(synth.WORKLOADS["gi"])
+    t = time.perf_counter()
+    ls = synth.abc_lineset(w["n_curves"], w["n_vertices"], w["seed"], w["perturb"])
+    log(f"[bench] gi workload generated in {time.perf_counter() - t:.1f}s")
+    grid, bins = w["grid"], w["bins"]
+    cam = synth.default_camera((grid,) * 3, w["width"], w["height"], w["orthographic"])
+    light = synth.LIGHT_DIR
+    with torch.cuda.stream(stream):
+        xyz = torch.as_tensor(ls.xyz).to(dev)
+        off = torch.as_tensor(ls.curve_off).to(dev)
+        attr = torch.as_tensor(ls.attr).to(dev)
+        lut = torch.as_tensor(synth.lut_importance_alpha()).to(dev)
+        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+    stream.synchronize()
+    n_vert = int(xyz.shape[0])
+    del ls
+    rp = dict(radius=w["radius"], opaque=False, alpha_stop=0.95, merge_curves=True, shading=2,
+              light_dir=light)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    ph = {"voxelize": [], "lod_illum": [], "render": []}
+    for r in range(reps + 1):
+        e = [ev() for _ in range(4)]
+        with torch.cuda.stream(stream):
+            e[0].record(stream)
+            s = L.lineset_voxelize(off, grid, bins, xyz=xyz, attr=attr, stream=stream)
+            e[1].record(stream)
+            L.lineset_build_lod(s, lut, opaque=False, build_ao=True, ao_cones=16, ao_radius=15.0,
+                                build_shadow=True, light_dir=light, stream=stream)
+            e[2].record(stream)
+            L.lineset_render(s, cam, lut, out=out, stream=stream, **rp)
+            e[3].record(stream)
+        stream.synchronize()
+        if r > 0:
+            ph["voxelize"].append(e[0].elapsed_time(e[1]))
+            ph["lod_illum"].append(e[1].elapsed_time(e[2]))
+            ph["render"].append(e[2].elapsed_time(e[3]))
+        if r < reps:
+            s.close()
+    _, cnt = L.lineset_render_counted(s, cam, lut, out=out, stream=stream, **rp)
+    info = s.info()
+    s.close()
+    med = {k: float(np.median(v)) for k, v in ph.items()}
+    rays = cam.width * cam.height
+    render_bytes = cnt["list_bytes"] + 16 * rays
+    G3 = grid ** 3
+    res = {
+        "workload": (f"gi: {w['n_curves']} curves x {w['n_vertices']} vertices, {grid}^3 grid, "
+                     f"{bins}^2 bins, r={w['radius']}, transparent, 16-cone AO + soft shadow, "
+                     f"{cam.width}x{cam.height} perspective"),
+        "records": int(info.n_records),
+        "phases_ms_median": med,
+        "step_ms": sum(med.values()),
+        "step_mrays_s": rays / (sum(med.values()) * 1e-3) / 1e6,
+        "render_mrays_s": rays / (med["render"] * 1e-3) / 1e6,
+        "voxelize_min_bytes": 12 * n_vert + 9 * (int(off.shape[0]) - 1) + 8 * int(info.n_records)
+        + 4 * (G3 + 1),
+        "render_roofline": {
+            "kernel": "k_render (ray caster)", "bound": "hbm",
+            "algorithmic_bytes_per_launch": int(render_bytes),
+            "achieved": render_bytes / (med["render"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": render_bytes / (med["render"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "counters": cnt,
+    }
+    res["voxelize_frac_hbm"] = (res["voxelize_min_bytes"] / (med["voxelize"] * 1e-3) / 1e9
+                                / HBM_PEAK_GBS)
+    log(f"[bench] gi: {res}")
+    del xyz, off, attr, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def vdi_leg(L, synth, torch, dev, stream, s, cam, lut_op, lut_tr, light, reps=5):
+    """View-dependent illumination on the resident scale set (its pyramid,
+    grids and representative lines built): 1920x1080 frames with the
+    per-fragment sources, opaque and transparent, against the per-voxel
+    grids."""
+    L.lineset_build_lod(s, lut_tr, opaque=False, build_ao=True, build_shadow=True,
+                        light_dir=light, build_rep_lines=True, stream=stream)
+    out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    cases = {
+        "grids": dict(),
+        "hemisphere_ao_16": dict(ao_mode=1, ao_rays=16, ao_radius=15.0),
+        "cone_shadow": dict(shadow_mode=1),
+        "rep_shadow_level1": dict(shadow_mode=2, rep_level=1),
+        "rep_shadow_level2": dict(shadow_mode=2, rep_level=2),
+    }
+    res = {}
+    for opaque in (True, False):
+        for name, kw in cases.items():
+            p = dict(radius=0.4, opaque=opaque, alpha_stop=0.95, merge_curves=True, shading=2,
+                     light_dir=light, **kw)
+            lut = lut_op if opaque else lut_tr
+            with torch.cuda.stream(stream):
+                L.lineset_render(s, cam, lut, out=out, stream=stream, **p)
+                e0, e1 = ev(), ev()
+                e0.record(stream)
+                for _ in range(reps):
+                    L.lineset_render(s, cam, lut, out=out, stream=stream, **p)
+                e1.record(stream)
+            stream.synchronize()
+            res[f"{'opaque' if opaque else 'transparent'}_{name}_ms"] = e0.elapsed_time(e1) / reps
+    log(f"[bench] view-dependent illumination: {res}")
+    return {"workload": "scale set, 1920x1080 perspective, shading 2 sources", **res}
+
+
 def _lod_dims(grid):
     """Level sizes of the density pyramid of a cubic grid (halving to 1)."""
     dims, g = [], grid
@@ -323,6 +495,8 @@ def serve_sweep(L, synth, torch, dev, rates, seconds_per_rate, max_requests,
                             None, **params)
             pending.append((tk, wh))
             offered += r["width"] * r["height"]
+            if (k + 1) % 250 == 0:
+                log(f"[bench] serve {lam:g} req/s: {k + 1}/{n_req} submitted")
         span = time.perf_counter() - t0
         collect(True)
         st = srv.stats()
@@ -426,12 +600,15 @@ def main():
     achieved = render_bytes / (render_ms * 1e-3) / 1e9
     med = {k: float(np.median(v)) for k, v in phase_ms.items()}
     traffic = None
+    counters_profiled = None
     if RENDER_TRAFFIC is not None:
         import hashlib
         src = os.path.join(ROOT, "paper_1801_01155_amd", "csrc", "render.hip")
         with open(src, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() == RENDER_TRAFFIC["render_hip_sha256"]:
                 traffic = RENDER_TRAFFIC["bytes_per_launch"]
+                counters_profiled = dict(RENDER_COUNTERS)
+    valu_tflops = cnt["tested"] * CAPSULE_FLOPS / (render_ms * 1e-3) / 1e12
     # minimum HBM bytes per phase (inputs read once, outputs written once)
     G3 = grid ** 3
     n_rec = int(info.n_records)
@@ -485,13 +662,29 @@ def main():
             "traffic_GB_s": (traffic / (render_ms * 1e-3) / 1e9) if traffic else None,
             "algorithmic_bytes_per_launch": int(render_bytes),
             "avg_launch_ms": render_ms,
+            # the other ceilings and what limits the kernel: capsule-test
+            # arithmetic against the fp32 vector peak, and the profiled L2 hit
+            # rate, lane use and wait share of this kernel source (null once
+            # the source has changed since the counters were taken)
+            "valu": {"achieved_tflops": valu_tflops, "peak_tflops": VALU_PEAK_TFLOPS,
+                     "frac": valu_tflops / VALU_PEAK_TFLOPS,
+                     "flops_per_test": CAPSULE_FLOPS, "tests": int(cnt["tested"])},
+            "profiled": counters_profiled,
+            "limiter": ("memory latency and divergence: a wave's time is its slowest "
+                        "ray's; HBM and VALU both far below their peaks"),
         },
         "phase_rooflines": phase_roof,
         "counters": cnt,
     }
+    if not args.no_vdi:
+        result["view_dependent"] = vdi_leg(L, synth, torch, dev, stream, s, cam,
+                                           torch.as_tensor(synth.lut_ramp(1.0)).to(dev), lut,
+                                           light)
     s.close()
     if not args.no_update:
         result["update"] = update_leg(L, synth, torch, dev, stream, ls, w)
+    if not args.no_gi:
+        result["gi"] = gi_leg(L, synth, torch, dev, stream)
     if not args.no_batch:
         result["batched"] = batched_vs_plain(L, synth, torch, dev, stream, max(3, args.steps // 2))
     if not args.no_serve:

@@ -93,6 +93,16 @@ int lineset_grid_setup(const float* xyz, int64_t n_vertices, const int32_t grid[
  *   Faces 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; (u, w) are the face's other
  *   two axes in increasing order.
  *
+ * Per-vertex attributes (section "Curve voxelization": line attributes
+ * interpolated to the line-face intersection points): with vertex_attr each
+ * event on segment v_i -> v_{i+1} at exact parameter t gets
+ * a_i + (a_{i+1} - a_i) t rounded to the nearest integer (halves up); every
+ * line keeps its entry and exit attributes (LS_EXPORT_ENDS, uint16
+ * entry | exit << 8 per record, CSR order) and its record's attribute byte is
+ * their mean rounded down (curve_attr is then ignored). Rendering reads the
+ * transfer function linearly at the attribute interpolated along the line at
+ * the segment point closest to the fragment's entry. Such sets are not
+ * updated in place (lineset_update returns LS_EUNSUPPORTED).
  * Errors: LS_EINVAL for grid sides outside [1, 1024] (3 with xyz input),
  * more than 2^30 voxels, bins not a power of two in [1, 64], non-monotone
  * curve_off, a lattice coordinate out of range; LS_ENOMEM if the lines
@@ -105,9 +115,10 @@ typedef struct {
   const uint8_t* curve_attr; /* [n_curves], or NULL for 255 */
   int64_t n_vertices;
   int64_t n_curves;
-  int32_t on_device;         /* 1: the four pointers are device memory; 0: host */
+  int32_t on_device;         /* 1: the pointers are device memory; 0: host */
   int32_t grid[3];
   int32_t bins;              /* N */
+  const uint8_t* vertex_attr; /* [n_vertices] per-vertex attribute, or NULL (see below) */
 } ls_voxelize_desc;
 
 int lineset_voxelize(const ls_voxelize_desc* desc, void* hip_stream, ls_lineset_t* out);
@@ -337,6 +348,19 @@ typedef struct {
 
 int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, void* hip_stream,
                          ls_batch_t* out);
+/* The plans the autotuner times, in its order: tile shape (waves_x x
+ * waves_y waves) and persistent grid size (grid_mult x CUs x workgroups per
+ * CU). Writes min(cap, count) entries and the count to *n. */
+int lineset_batch_candidates(int32_t* waves_x, int32_t* waves_y, int32_t* grid_mult, int32_t cap,
+                             int32_t* n);
+/* lineset_batch_create with a fixed plan (one of the candidates' tile shapes,
+ * grid_mult in [1, 8]; no autotuning, no plan cache; flags may hold
+ * LS_BATCH_GRAPH only), so every plan the autotuner can pick can be run and
+ * checked. Errors: LS_EINVAL for an unknown shape or multiplier, or with
+ * LS_BATCH_AUTOTUNE; otherwise as lineset_batch_create. */
+int lineset_batch_create_plan(const ls_view* views, int32_t n_views, int32_t waves_x,
+                              int32_t waves_y, int32_t grid_mult, int32_t flags, void* hip_stream,
+                              ls_batch_t* out);
 int lineset_batch_render(ls_batch_t batch, void* hip_stream);
 int lineset_batch_render_counted(ls_batch_t batch, ls_render_counters* counters,
                                  void* hip_stream);
@@ -470,6 +494,7 @@ typedef struct {
   int32_t n_levels;          /* density pyramid levels (0 before build_lod) */
   int32_t has_ao, has_shadow;
   int32_t has_rep_lines;
+  int32_t has_vertex_attr;   /* per-line endpoint attributes (LS_EXPORT_ENDS) */
   int32_t level_dims[32][3];
   int64_t level_off[33];
   double lo_scale[4];        /* grid set-up of xyz input: lo[3], S */
@@ -486,7 +511,8 @@ enum {
   LS_EXPORT_LOD_RHO = 4,
   LS_EXPORT_AO = 5,          /* float [voxels] */
   LS_EXPORT_SHADOW = 6,      /* float [voxels] */
-  LS_EXPORT_REP_LINES = 7    /* uint32, all levels flat (level_off) */
+  LS_EXPORT_REP_LINES = 7,   /* uint32, all levels flat (level_off) */
+  LS_EXPORT_ENDS = 8         /* uint16 [n_records]: entry | exit << 8 attributes */
 };
 
 /* Copies one buffer of the set into `dst` (host or device). Errors:

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblineset.so")
 
 LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EUNSUPPORTED, LS_EBUSY, LS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 (EXPORT_OFFSETS, EXPORT_RECORDS, EXPORT_LOD_COUNT, EXPORT_LOD_LEN, EXPORT_LOD_RHO, EXPORT_AO,
- EXPORT_SHADOW, EXPORT_REP_LINES) = range(8)
+ EXPORT_SHADOW, EXPORT_REP_LINES, EXPORT_ENDS) = range(9)
 
 
 class LinesetError(RuntimeError):
@@ -31,7 +31,8 @@ class LinesetError(RuntimeError):
 class VoxelizeDesc(C.Structure):
     _fields_ = [("xyz", C.c_void_p), ("lattice", C.c_void_p), ("curve_off", C.c_void_p),
                 ("curve_attr", C.c_void_p), ("n_vertices", C.c_int64), ("n_curves", C.c_int64),
-                ("on_device", C.c_int32), ("grid", C.c_int32 * 3), ("bins", C.c_int32)]
+                ("on_device", C.c_int32), ("grid", C.c_int32 * 3), ("bins", C.c_int32),
+                ("vertex_attr", C.c_void_p)]
 
 
 class LodDesc(C.Structure):
@@ -73,6 +74,7 @@ class Info(C.Structure):
                 ("n_record_slots", C.c_int64), ("nonempty_voxels", C.c_int64),
                 ("max_list", C.c_int64), ("n_levels", C.c_int32), ("has_ao", C.c_int32),
                 ("has_shadow", C.c_int32), ("has_rep_lines", C.c_int32),
+                ("has_vertex_attr", C.c_int32),
                 ("level_dims", (C.c_int32 * 3) * 32),
                 ("level_off", C.c_int64 * 33), ("lo_scale", C.c_double * 4),
                 ("device_bytes", C.c_size_t)]
@@ -167,7 +169,9 @@ class LineSet:
 
 
 def lineset_voxelize(curve_off, grid, bins=32, xyz=None, lattice=None, attr=None,
-                     stream=None) -> LineSet:
+                     stream=None, vattr=None) -> LineSet:
+    """vattr: optional per-vertex attribute bytes (interpolated to the face
+    crossings; the lines keep their endpoint attributes)."""
     d = VoxelizeDesc()
     keep = []
     if xyz is not None:
@@ -188,6 +192,10 @@ def lineset_voxelize(curve_off, grid, bins=32, xyz=None, lattice=None, attr=None
         attr = _dev(attr, torch.uint8)
         keep.append(attr)
         d.curve_attr = attr.data_ptr()
+    if vattr is not None:
+        vattr = _dev(vattr, torch.uint8)
+        keep.append(vattr)
+        d.vertex_attr = vattr.data_ptr()
     d.on_device = 1
     d.grid = _grid3(grid)
     d.bins = bins
@@ -337,7 +345,8 @@ def lineset_pool_stats(device: int = 0) -> dict:
 _EXPORT_DTYPE = {EXPORT_OFFSETS: torch.int32, EXPORT_RECORDS: torch.int64,
                  EXPORT_LOD_COUNT: torch.float32, EXPORT_LOD_LEN: torch.float32,
                  EXPORT_LOD_RHO: torch.float32, EXPORT_AO: torch.float32,
-                 EXPORT_SHADOW: torch.float32, EXPORT_REP_LINES: torch.int32}
+                 EXPORT_SHADOW: torch.float32, EXPORT_REP_LINES: torch.int32,
+                 EXPORT_ENDS: torch.int16}
 
 
 def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
@@ -350,7 +359,8 @@ def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
          EXPORT_LOD_LEN: i.level_off[i.n_levels] if i.n_levels else 0,
          EXPORT_LOD_RHO: i.level_off[i.n_levels] if i.n_levels else 0,
          EXPORT_AO: nvox, EXPORT_SHADOW: nvox,
-         EXPORT_REP_LINES: i.level_off[i.n_levels] if i.has_rep_lines else 0}[what]
+         EXPORT_REP_LINES: i.level_off[i.n_levels] if i.has_rep_lines else 0,
+         EXPORT_ENDS: i.n_records if i.has_vertex_attr else 0}[what]
     t = torch.empty(max(int(n), 1), dtype=_EXPORT_DTYPE[what], device="cuda")
     _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
                                 _stream(stream)))
@@ -382,6 +392,12 @@ def _bind_batch(L):
         return
     L.lineset_batch_create.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_int32, C.c_void_p,
                                        C.POINTER(C.c_void_p)]
+    L.lineset_batch_create_plan.argtypes = [C.POINTER(ViewS), C.c_int32, C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_void_p,
+                                            C.POINTER(C.c_void_p)]
+    L.lineset_batch_candidates.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32), C.c_int32,
+                                           C.POINTER(C.c_int32)]
     L.lineset_batch_render.argtypes = [C.c_void_p, C.c_void_p]
     L.lineset_batch_render_counted.argtypes = [C.c_void_p, C.POINTER(RenderCounters), C.c_void_p]
     L.lineset_batch_config.argtypes = [C.c_void_p, C.POINTER(BatchConfig)]
@@ -406,15 +422,22 @@ def make_views(items):
 class Batch:
     """Owns an ls_batch_t (one persistent launch over many views)."""
 
-    def __init__(self, items, autotune=False, graph=False, stream=None):
+    def __init__(self, items, autotune=False, graph=False, stream=None, plan=None):
+        """plan: (waves_x, waves_y, grid_mult) to fix the plan (one of
+        batch_candidates()) instead of the cache / autotuner / default."""
         L = lib()
         _bind_batch(L)
         self._items = list(items)      # keep sets, LUTs and outputs alive
         self._views = make_views(self._items)
         flags = (BATCH_AUTOTUNE if autotune else 0) | (BATCH_GRAPH if graph else 0)
         h = C.c_void_p()
-        _check(L.lineset_batch_create(self._views, len(self._items), flags, _stream(stream),
-                                      C.byref(h)))
+        if plan is None:
+            _check(L.lineset_batch_create(self._views, len(self._items), flags, _stream(stream),
+                                          C.byref(h)))
+        else:
+            wx, wy, m = plan
+            _check(L.lineset_batch_create_plan(self._views, len(self._items), wx, wy, m, flags,
+                                               _stream(stream), C.byref(h)))
         self.handle = h
 
     def render(self, stream=None):
@@ -437,6 +460,17 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def batch_candidates():
+    """The autotuner's plans [(waves_x, waves_y, grid_mult), ...] in its order."""
+    L = lib()
+    _bind_batch(L)
+    n = C.c_int32()
+    _check(L.lineset_batch_candidates(None, None, None, 0, C.byref(n)))
+    wx, wy, m = (C.c_int32 * n.value)(), (C.c_int32 * n.value)(), (C.c_int32 * n.value)()
+    _check(L.lineset_batch_candidates(wx, wy, m, n.value, C.byref(n)))
+    return [(wx[k], wy[k], m[k]) for k in range(n.value)]
 
 
 def lineset_render_batch(items, stream=None):

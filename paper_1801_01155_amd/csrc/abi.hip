@@ -126,7 +126,7 @@ int ls_alloc(ls_lineset* s, void** p, size_t bytes) {
 
 void ls_free_all(ls_lineset* s) {
   void* ptrs[] = {s->offsets, s->records, s->occupancy, s->lod_count, s->lod_len,
-                  s->lod_rho, s->ao,      s->sh,        s->cone_tab, s->rep};
+                  s->lod_rho, s->ao,      s->sh,        s->cone_tab, s->rep, s->ends};
   bool any = false;
   for (void* p : ptrs) any = any || p;
   // work queued on any stream may still read the set (hipFree would wait too)
@@ -141,6 +141,7 @@ void ls_free_all(ls_lineset* s) {
   s->cone_tab_bytes = 0;
   s->rep = nullptr;
   s->rep_levels = 0;
+  s->ends = nullptr;
   s->bytes = 0;
 }
 
@@ -293,20 +294,24 @@ int lineset_voxelize(const ls_voxelize_desc* d, void* hip_stream, ls_lineset_t* 
   const int32_t* lat = nullptr;
   const int64_t* off = nullptr;
   const uint8_t* attr = nullptr;
+  const uint8_t* vattr = nullptr;
   {
     float* x = nullptr;
     int32_t* l = nullptr;
     int64_t* o = nullptr;
     uint8_t* a = nullptr;
+    uint8_t* va = nullptr;
     if ((rc = to_device(d->xyz, 3 * d->n_vertices, d->on_device, &x, own.v, st)) ||
         (rc = to_device(d->lattice, 3 * d->n_vertices, d->on_device, &l, own.v, st)) ||
         (rc = to_device(d->curve_off, d->n_curves + 1, d->on_device, &o, own.v, st)) ||
-        (rc = to_device(d->curve_attr, d->n_curves, d->on_device, &a, own.v, st)))
+        (rc = to_device(d->curve_attr, d->n_curves, d->on_device, &a, own.v, st)) ||
+        (rc = to_device(d->vertex_attr, d->n_vertices, d->on_device, &va, own.v, st)))
       return rc;
     xyz = x;
     lat = l;
     off = o;
     attr = a;
+    vattr = va;
   }
 
   ls_lineset* s = new (std::nothrow) ls_lineset();
@@ -320,7 +325,7 @@ int lineset_voxelize(const ls_voxelize_desc* d, void* hip_stream, ls_lineset_t* 
   s->n_curves = d->n_curves;
   s->n_vertices = d->n_vertices;
   s->device = dev;
-  if ((rc = vox_build(s, xyz, lat, off, attr, st))) {
+  if ((rc = vox_build(s, xyz, lat, off, attr, vattr, st))) {
     (void)hipStreamSynchronize(st);
     ls_free_all(s);
     delete s;
@@ -461,6 +466,7 @@ int lineset_info(ls_lineset_t s, ls_info* o) {
   o->has_ao = s->ao != nullptr;
   o->has_shadow = s->sh != nullptr;
   o->has_rep_lines = s->rep != nullptr;
+  o->has_vertex_attr = s->ends != nullptr;
   for (int l = 0; l < s->n_levels && l < 32; ++l)
     for (int a = 0; a < 3; ++a) o->level_dims[l][a] = s->level_dims[l][a];
   for (int l = 0; l <= s->n_levels && l < 33; ++l) o->level_off[l] = s->level_off[l];
@@ -486,6 +492,10 @@ int lineset_export(ls_lineset_t s, int32_t what, void* dst, size_t dst_bytes,
     case LS_EXPORT_LOD_RHO: src = s->lod_rho; bytes = lod_bytes; break;
     case LS_EXPORT_AO: src = s->ao; bytes = s->ao ? sizeof(float) * (size_t)s->nvox : 0; break;
     case LS_EXPORT_SHADOW: src = s->sh; bytes = s->sh ? sizeof(float) * (size_t)s->nvox : 0; break;
+    case LS_EXPORT_ENDS:
+      src = s->ends;
+      bytes = s->ends ? sizeof(uint16_t) * (size_t)s->n_records : 0;
+      break;
     case LS_EXPORT_REP_LINES:
       src = s->rep;
       bytes = s->rep ? sizeof(uint32_t) * (size_t)s->level_off[s->rep_levels] : 0;

@@ -42,8 +42,10 @@ constexpr int kQueueWords = 8 + (int)(sizeof(RenderCounters) / sizeof(unsigned))
 std::mutex g_cache_mu;
 std::map<std::string, BatchPlan> g_plan_cache;
 
-bool view_dependent_params(const ls_render_params& p) {
-  return p.shading == 2 && (p.ao_mode != 0 || p.shadow_mode != 0);
+// The extended kernel instance (see view_dependent in render_args.h).
+bool view_dependent_params(const ls_view& v) {
+  return (v.params.shading == 2 && (v.params.ao_mode != 0 || v.params.shadow_mode != 0)) ||
+         (v.set && v.set->ends != nullptr);
 }
 
 std::string signature(const std::vector<ls_view>& v) {
@@ -51,7 +53,7 @@ std::string signature(const std::vector<ls_view>& v) {
   for (const auto& x : v) {
     k += std::to_string(x.cam.width) + "x" + std::to_string(x.cam.height) + "m" +
          std::to_string(x.params.mode) + "o" + std::to_string(x.params.opaque) +
-         (view_dependent_params(x.params) ? "v;" : ";");
+         (view_dependent_params(x) ? "v;" : ";");
   }
   return k;
 }
@@ -118,9 +120,12 @@ int plan_blocks(int wx, int wy, int mult, bool vdi, int* blocks) {
 
 // Times every candidate (tile shape x persistent grid size) on this batch and
 // keeps the fastest; results are cached per batch signature.
+constexpr int kShapes[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {1, 2}, {1, 1}};
+constexpr int kMults[] = {1, 2};
+
 int autotune(ls_batch* b, hipStream_t st) {
-  static const int shapes[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {1, 2}, {1, 1}};
-  static const int mults[] = {1, 2};
+  const auto& shapes = kShapes;
+  const auto& mults = kMults;
   hipEvent_t e0, e1;
   LS_HIP(hipEventCreate(&e0));
   LS_HIP(hipEventCreate(&e1));
@@ -222,8 +227,10 @@ int static_scratch(int dev, unsigned char** out) {
 
 extern "C" {
 
-int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, void* hip_stream,
-                         ls_batch_t* out) {
+// fixed: a plan (wx, wy, grid multiplier) chosen by the caller instead of the
+// cache / autotuner / default.
+static int create_batch(const ls_view* views, int32_t n_views, int32_t flags, const int32_t* fixed,
+                        void* hip_stream, ls_batch_t* out) {
   if (!out) {
     ls_set_error("lineset_batch_create: out is NULL");
     return LS_EINVAL;
@@ -247,7 +254,7 @@ int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, v
   b->n_views = n_views;
   b->flags = flags;
   b->views.assign(views, views + n_views);
-  for (const ls_view& x : b->views) b->vdi = b->vdi || view_dependent_params(x.params);
+  for (const ls_view& x : b->views) b->vdi = b->vdi || view_dependent_params(x);
   (void)hipGetDevice(&b->device);
   auto fail = [&](int code) {
     (void)hipStreamSynchronize(st);
@@ -264,12 +271,16 @@ int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, v
   }
   const std::string key = signature(b->views);
   BatchPlan cached{0, 0, 0};
-  {
+  if (!fixed) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_plan_cache.find(key);
     if (it != g_plan_cache.end()) cached = it->second;
   }
-  if (cached.blocks > 0) {
+  if (fixed) {
+    BatchPlan p{fixed[0], fixed[1], 0};
+    rc = plan_blocks(p.wx, p.wy, fixed[2], b->vdi, &p.blocks);
+    if (!rc) rc = prepare(b, p, st);
+  } else if (cached.blocks > 0) {
     rc = prepare(b, cached, st);
     b->autotuned = 2;  // from the cache
   } else if (flags & LS_BATCH_AUTOTUNE) {
@@ -287,6 +298,51 @@ int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, v
   if (rc) return fail(rc);
   *out = b;
   return LS_OK;
+}
+
+int lineset_batch_create(const ls_view* views, int32_t n_views, int32_t flags, void* hip_stream,
+                         ls_batch_t* out) {
+  return create_batch(views, n_views, flags, nullptr, hip_stream, out);
+}
+
+int lineset_batch_candidates(int32_t* waves_x, int32_t* waves_y, int32_t* grid_mult, int32_t cap,
+                             int32_t* n) {
+  if (!n || (cap > 0 && (!waves_x || !waves_y || !grid_mult))) {
+    ls_set_error("lineset_batch_candidates: null argument");
+    return LS_EINVAL;
+  }
+  int k = 0;
+  for (const auto& sh : kShapes)
+    for (int m : kMults) {
+      if (k < cap) {
+        waves_x[k] = sh[0];
+        waves_y[k] = sh[1];
+        grid_mult[k] = m;
+      }
+      ++k;
+    }
+  *n = k;
+  return LS_OK;
+}
+
+int lineset_batch_create_plan(const ls_view* views, int32_t n_views, int32_t waves_x,
+                              int32_t waves_y, int32_t grid_mult, int32_t flags, void* hip_stream,
+                              ls_batch_t* out) {
+  bool known = false;
+  for (const auto& sh : kShapes) known = known || (sh[0] == waves_x && sh[1] == waves_y);
+  if (!known || grid_mult < 1 || grid_mult > 8) {
+    if (out) *out = nullptr;
+    ls_set_error("lineset_batch_create_plan: tile shape not one of the candidates, or grid "
+                 "multiplier outside [1, 8]");
+    return LS_EINVAL;
+  }
+  if (flags & LS_BATCH_AUTOTUNE) {
+    if (out) *out = nullptr;
+    ls_set_error("lineset_batch_create_plan: a fixed plan is not autotuned");
+    return LS_EINVAL;
+  }
+  const int32_t fixed[3] = {waves_x, waves_y, grid_mult};
+  return create_batch(views, n_views, flags, fixed, hip_stream, out);
 }
 
 int lineset_batch_render(ls_batch_t b, void* hip_stream) {
@@ -364,7 +420,7 @@ int lineset_render_batch_static(const ls_view* views, int32_t n_views, void* hip
   int32_t tile_start[kStaticViews + 1];
   BatchPlan plan{2, 2, 0};
   bool vdi = false;
-  for (int v = 0; v < n_views; ++v) vdi = vdi || view_dependent_params(views[v].params);
+  for (int v = 0; v < n_views; ++v) vdi = vdi || view_dependent_params(views[v]);
   if ((rc = plan_blocks(plan.wx, plan.wy, 1, vdi, &plan.blocks))) return rc;
   int64_t total = 0;
   for (int v = 0; v < n_views; ++v) {

@@ -38,6 +38,7 @@ struct ls_lineset {
   bool stats_pending;  // nonempty and max_list still on the device (after the occupancy words)
   uint32_t* offsets;   // [nvox + 1]
   uint64_t* records;   // [n_records] (at least one element allocated)
+  uint16_t* ends;      // [n_records] endpoint attributes entry | exit << 8 (per-vertex input), or null
   uint64_t* occupancy; // per 4^3 macro cell: 64-bit mask of its non-empty voxels;
                        // then the non-empty voxel count (u64) and the longest list (u32)
   int32_t macro[3];    // macro-cell grid dims (ceil(grid / 4))
@@ -94,7 +95,7 @@ int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_
 // Builds the set's CSR. Float input (xyz): the grid set-up runs on the
 // device and s->lo_scale is set; lattice input (lat): used as given.
 int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
-              const uint8_t* attr, hipStream_t st);
+              const uint8_t* attr, const uint8_t* vattr, hipStream_t st);
 // Occupancy words and list statistics of s->offsets (allocates s->occupancy).
 int vox_occupancy(ls_lineset* s, hipStream_t st);
 

@@ -485,13 +485,31 @@ __device__ inline bool rep_shadow(const RenderArgs& R, const int32_t cell[3], co
 // Shade and composite one fragment. p is the entry point in the frame of
 // `cell`, a/b the record's endpoints in the same frame, dt the ray-parameter
 // length of the hit (exit - entry).
+// Transfer function at the line attribute interpolated along the line (the
+// record's endpoint attributes taken linearly at the segment point closest
+// to p), read linearly between its two neighbouring entries.
+__device__ inline float4 lut_along(const float4* lut_lds, uint32_t en, const float p[3],
+                                   const float a[3], const float b[3]) {
+  #pragma clang fp contract(fast)
+  const float ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  const float pa[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+  const float u = fminf(fmaxf(dot3(pa, ba) / dot3(ba, ba), 0.f), 1.f);
+  const float e = (float)(en & 0xFFu), x = (float)(en >> 8);
+  const float af = e + u * (x - e);
+  const int i0 = min((int)floorf(af), 255), i1 = min(i0 + 1, 255);
+  const float f = af - (float)i0;
+  const float4 l0 = lut_lds[i0], l1 = lut_lds[i1];
+  return make_float4(l0.x + f * (l1.x - l0.x), l0.y + f * (l1.y - l0.y), l0.z + f * (l1.z - l0.z),
+                     l0.w + f * (l1.w - l0.w));
+}
+
 template <bool kVdi>
 __device__ __attribute__((always_inline)) inline void composite(const RenderArgs& R, const float4* lut_lds, const Shade& S, Accum& acc, uint64_t rec,
-                                 const int32_t cell[3], const float p[3], const float a[3],
-                                 const float b[3], float dt, Counts& cnt) {
+                                 uint32_t k, const int32_t cell[3], const float p[3],
+                                 const float a[3], const float b[3], float dt, Counts& cnt) {
   #pragma clang fp contract(fast)
   const int attr = (int)((rec >> 32) & 0xFF);
-  const float4 lut = lut_lds[attr];
+  const float4 lut = (kVdi && R.ends) ? lut_along(lut_lds, R.ends[k], p, a, b) : lut_lds[attr];
   const float alpha = fragment_alpha(R, lut.w, dt * S.dlen);
   float col[3] = {lut.x, lut.y, lut.z};
   if (R.shading != 0) {
@@ -873,7 +891,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + best * ray.d[c];
-        composite<kVdi>(R, lut_lds, S, acc, rec, vcell, p, a, b, 0.f, cnt);
+        composite<kVdi>(R, lut_lds, S, acc, rec, bi, vcell, p, a, b, 0.f, cnt);
         acc.done = true;
       }
     }
@@ -936,7 +954,8 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
       const bool more = buf.dropped != 0;
       while (buf.n > 0 && !acc.done) {
         const float t_in = buf.t[0], t_out = buf.so[0];
-        const uint64_t rc = R.records[buf.idx[0]];
+        const uint32_t ki = buf.idx[0];
+        const uint64_t rc = R.records[ki];
         buf.pop_front();
         if (R.merge) {
           const uint32_t tag = (uint32_t)(rc >> 40);
@@ -947,7 +966,7 @@ __device__ __attribute__((always_inline)) inline void voxels_coop(
         decode_point((uint32_t)((rc >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c] = q[c] + t_in * ray.d[c];
-        composite<kVdi>(R, lut_lds, S, acc, rc, vcell, p, a, b, t_out - t_in, cnt);
+        composite<kVdi>(R, lut_lds, S, acc, rc, ki, vcell, p, a, b, t_out - t_in, cnt);
       }
       need = more && !acc.done;
       if (need) cnt.passes++;
@@ -1084,6 +1103,7 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       const float len = buf.so[0];
       const int nb = (int)buf.aux[0];
       const uint64_t rec = buf.rec[0];
+      const uint32_t ki = buf.idx[0];
       buf.pop_front();
       if (!R.opaque && R.merge) {
         const uint32_t tag = (uint32_t)(rec >> 40);
@@ -1099,7 +1119,7 @@ __device__ __attribute__((always_inline)) inline void voxel_exact(const RenderAr
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), R.inv_bins, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c] = q[c] + s_in * ray.d[c];
-      composite<kVdi>(R, lut_lds, S, acc, rec, w, p, a, b, len, cnt);
+      composite<kVdi>(R, lut_lds, S, acc, rec, ki, w, p, a, b, len, cnt);
       if (R.opaque) acc.done = true;
     }
     if (acc.done || !more) break;
@@ -1447,6 +1467,7 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.n_levels = s->lod_rho ? s->n_levels : 0;
   R.rho = s->lod_rho;
   R.rep = s->rep;
+  R.ends = s->ends;
   R.out = out;
   R.counters = dev_counters;
   R.wx = wx;

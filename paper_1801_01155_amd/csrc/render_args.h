@@ -29,6 +29,7 @@ struct RenderArgs {
   float ao_radius;
   const float* rho;               // density pyramid, levels flat
   const uint32_t* rep;            // representative lines, levels flat
+  const uint16_t* ends;           // per-record endpoint attributes (or null)
   float* out;
   RenderCounters* counters;
   int32_t wx, wy;                 // tile = wx x wy waves of 8 x 8 pixels
@@ -57,10 +58,11 @@ struct BatchPlan {
 int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
                      float* out, int wx, int wy, RenderCounters* dev_counters, RenderArgs* R);
 int launch_render(const RenderArgs& R, hipStream_t st);
-// True when the view samples the pyramid or the representative lines per
-// fragment (the kernels' view-dependent illumination instance).
+// True when the view needs the kernels' extended instance: it samples the
+// pyramid or the representative lines per fragment (view-dependent
+// illumination), or its set carries per-line endpoint attributes.
 inline bool view_dependent(const RenderArgs& R) {
-  return R.shading == 2 && (R.ao_mode != 0 || R.shadow_mode != 0);
+  return (R.shading == 2 && (R.ao_mode != 0 || R.shadow_mode != 0)) || R.ends != nullptr;
 }
 BatchQueues make_queues(int total_tiles);
 // dev_queue: 8 queue counters (zeroed before the launch), followed by a

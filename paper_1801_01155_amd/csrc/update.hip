@@ -144,6 +144,11 @@ extern "C" int lineset_update(ls_lineset_t s, const ls_update_desc* d, void* hip
     ls_set_error("lineset_update: xyz needs a set voxelized from xyz (its grid set-up)");
     return LS_EINVAL;
   }
+  if (s->ends) {
+    ls_set_error("lineset_update: sets voxelized with per-vertex attributes are not updated "
+                 "in place (voxelize the edited curve list)");
+    return LS_EUNSUPPORTED;
+  }
   if (s->n_curves + d->n_curves > kMaxTagged) {
     ls_set_error("lineset_update: more than 2^24 curves (curve tags would repeat)");
     return LS_EUNSUPPORTED;
@@ -217,7 +222,7 @@ extern "C" int lineset_update(ls_lineset_t s, const ls_update_desc* d, void* hip
     add->device = s->device;
     // lattice input: vox_build checks the range (a vertex outside the grid
     // is an error, and the set stays as it was)
-    if ((rc = vox_build(add, nullptr, lat, off, attr, st))) return rc;
+    if ((rc = vox_build(add, nullptr, lat, off, attr, nullptr, st))) return rc;
   }
 
   // 2. removal mask over the old curve ids

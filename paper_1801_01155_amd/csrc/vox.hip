@@ -279,6 +279,7 @@ struct Last {
   int has;
   long long xn0, xn1, xn2, den;
   unsigned entry;
+  unsigned attr;   // vertex attribute interpolated to the event (attribute input)
 };
 
 __device__ inline Last shfl_last(const Last& v, int src) {
@@ -289,7 +290,16 @@ __device__ inline Last shfl_last(const Last& v, int src) {
   o.xn2 = __shfl(v.xn2, src, 64);
   o.den = __shfl(v.den, src, 64);
   o.entry = __shfl(v.entry, src, 64);
+  o.attr = __shfl(v.attr, src, 64);
   return o;
+}
+
+// Section "Curve voxelization": a line attribute interpolated to the face
+// crossing at parameter num / den of the segment whose vertices carry a0 and
+// a1, rounded to the nearest integer (halves up), exactly.
+__device__ inline unsigned event_attr(unsigned a0, unsigned a1, long long num, long long den) {
+  const long long s = 2 * ((long long)a0 * den + ((long long)a1 - (long long)a0) * num) + den;
+  return (unsigned)(s / (2 * den));
 }
 
 // Plane crossings of segment P0 -> P1 and its last event, without walking
@@ -298,7 +308,8 @@ __device__ inline Last shfl_last(const Last& v, int src) {
 // walk in for_each_event gives a simultaneous event), and it enters the
 // segment's final voxel.
 __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
-                                      const GridArgs& ga, Last& out) {
+                                      const GridArgs& ga, Last& out, unsigned a0 = 0,
+                                      unsigned a1 = 0) {
   int64_t d[3], num[3], dn[3];
   int32_t c1[3];
   uint32_t cross = 0;
@@ -342,6 +353,7 @@ __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
 #pragma unroll
   for (int b = 0; b < 3; ++b) xl[b] = (uint32_t)xn[b];
   out.entry = face_code(fa, df > 0 ? 0 : 1, xl, (int32_t)den, c1, ga);
+  out.attr = event_attr(a0, a1, nf, den);
   return cross;
 }
 
@@ -358,6 +370,7 @@ struct EmitRing {
   uint32_t entry[kEmitRing];
   int32_t den[kEmitRing];
   long long x[3][kEmitRing];
+  uint32_t va[kEmitRing];   // attribute input: a0 | a1 << 8 | (event before) << 16
 };
 
 // Lines of every curve in curve order: the line inside a voxel runs from
@@ -366,14 +379,17 @@ struct EmitRing {
 // ending at an event goes to slot slot_off[c] + (plane crossings of the curve
 // before that event) - 1; slots no line takes keep the invalid mark written
 // before the launch. Each line takes its rank in its voxel with one atomic on
-// the histogram.
-template <bool kFloatIn>
+// the histogram. With per-vertex attributes (kAttr) every event carries the
+// attribute interpolated to it; a line writes its two endpoint attributes to
+// ends_out and their mean (rounded down) as its record's attribute byte.
+template <bool kFloatIn, bool kAttr>
 __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int32_t* lat,
                                                  const int64_t* curve_off, const uint8_t* attr,
+                                                 const uint8_t* vattr,
                                                  int64_t n_curves, int64_t curve_base,
                                                  const SnapArgs* sap,
                                                  GridArgs ga, const uint64_t* slot_off,
-                                                 uint64_t* rec_out,
+                                                 uint64_t* rec_out, uint16_t* ends_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
                                                  uint32_t* hist) {
   __shared__ EmitRing rings[kWavesPerBlock];
@@ -404,7 +420,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     uint64_t g = Q.g[k];
     bool has_prev = bden != 0, first = true;
     uint32_t prev_entry = Q.entry[k];
+    const uint32_t va = kAttr ? Q.va[k] : 0u;
+    uint32_t prev_attr = va >> 16;
     for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
+      const uint32_t ea = kAttr ? event_attr(va & 0xFFu, (va >> 8) & 0xFFu, ev.nf, ev.den) : 0u;
       if (has_prev) {
         const uint64_t w = w0 + (g - 1);
         if (w < w_end) {
@@ -421,7 +440,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
           }
           if (!same && prev_entry != ev.exit_code) {
             const uint32_t vid = (uint32_t)(cell[0] + gx * cell[1] + gxy * cell[2]);
-            rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hi_bits;
+            uint64_t hb = hi_bits;
+            if (kAttr) {
+              hb = (hb & ~(0xFFull << 32)) | ((uint64_t)((prev_attr + ea) >> 1) << 32);
+              ends_out[w] = (uint16_t)(prev_attr | (ea << 8));
+            }
+            rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hb;
             vox_out[w] = vid;
             rank_out[w] = atomicAdd(hist + vid, 1u);
           }
@@ -430,11 +454,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
       has_prev = true;
       first = false;
       prev_entry = ev.entry_code;
+      prev_attr = ea;
       g += (uint64_t)ev.planes;
     });
   };
 
-  Last carry{0, 0, 0, 0, 1, 0u};
+  Last carry{0, 0, 0, 0, 1, 0u, 0u};
   uint64_t g0 = 0;       // crossings of the curve before this chunk
   uint32_t q_head = 0, q_n = 0;   // ring state (wave-uniform)
   for (int64_t s0 = v0; s0 + 1 < v1; s0 += 64) {
@@ -449,8 +474,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     // (an event of k simultaneous planes uses k numbers), so the numbering
     // needs no walk; the unused numbers stay invalid slots.
     uint32_t e = 0;
-    Last mine{0, 0, 0, 0, 1, 0u};
-    if (valid) e = last_event(P0, P1, ga, mine);
+    Last mine{0, 0, 0, 0, 1, 0u, 0u};
+    uint32_t a01 = 0;
+    if (kAttr && valid) a01 = (uint32_t)vattr[i] | ((uint32_t)vattr[i + 1] << 8);
+    if (valid) e = last_event(P0, P1, ga, mine, a01 & 0xFFu, a01 >> 8);
     // exclusive prefix sum of the crossing counts
     uint32_t inc = e;
 #pragma unroll
@@ -488,6 +515,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
       Q.x[0][k] = before.xn0;
       Q.x[1][k] = before.xn1;
       Q.x[2][k] = before.xn2;
+      if (kAttr) Q.va[k] = a01 | (before.attr << 16);
     }
     q_n += (uint32_t)__popcll(am);
     // carry the chunk's last event
@@ -524,8 +552,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const u
 constexpr int kRankLds = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_rank(const uint64_t* idx, const uint64_t* rec,
-                                                 int64_t n_records, const uint32_t* offsets,
-                                                 uint64_t* records) {
+                                                 const uint16_t* ends_in, int64_t n_records,
+                                                 const uint32_t* offsets, uint64_t* records,
+                                                 uint16_t* ends) {
   __shared__ uint32_t s_idx[kRankLds];
   __shared__ uint32_t s_range[2];
   const int64_t p0 = (int64_t)blockIdx.x * kBlock;
@@ -555,6 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(const uint64_t* idx, const uint
     for (uint32_t q = lo; q < hi; ++q) r += (uint32_t)idx[q] < e;
   }
   records[lo + r] = rec[e];
+  if (ends) ends[lo + r] = ends_in[e];
 }
 
 // Occupancy mask per 4^3 macro cell: bit (x & 3) + 4 (y & 3) + 16 (z & 3) of
@@ -813,7 +843,7 @@ int vox_snap(const float* xyz, int64_t nv, SnapArgs sa, int32_t* lat, hipStream_
 }
 
 int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t* curve_off,
-              const uint8_t* attr, hipStream_t st) {
+              const uint8_t* attr, const uint8_t* vattr, hipStream_t st) {
   GridArgs ga;
   for (int a = 0; a < 3; ++a) ga.g[a] = s->grid[a];
   ga.bins = s->bins;
@@ -905,23 +935,36 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   if ((rc = fill_u32(s->offsets, 0u, s->nvox + 1, st))) return rc;
 
   // 3. emit
-  DeviceBuf rec(st), vox(st), rank(st), sums32(st);
+  DeviceBuf rec(st), vox(st), rank(st), sums32(st), ends_slots(st);
   if ((rc = rec.alloc(sizeof(uint64_t) * n_slots)) || (rc = vox.alloc(sizeof(uint32_t) * n_slots)) ||
       (rc = rank.alloc(sizeof(uint32_t) * n_slots)) ||
       (rc = sums32.alloc(sizeof(uint32_t) * scan_block_sums_len(s->nvox))))
     return rc;
+  if (vattr && (rc = ends_slots.alloc(sizeof(uint16_t) * (n_slots ? n_slots : 1)))) return rc;
   if ((rc = fill_u32(vox.as<uint32_t>(), LS_INVALID_VOXEL, (int64_t)n_slots, st))) return rc;
   if (C > 0) {
-    if (float_in)
-      hipLaunchKernelGGL((k_emit<true>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
-                         rec.as<uint64_t>(),
-                         vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
+    const dim3 grid(curve_blocks(C)), block(kBlock);
+    uint16_t* eo = vattr ? ends_slots.as<uint16_t>() : nullptr;
+    if (float_in && vattr)
+      hipLaunchKernelGGL((k_emit<true, true>), grid, block, 0, st, xyz, lat, curve_off, attr,
+                         vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
+                         s->offsets);
+    else if (float_in)
+      hipLaunchKernelGGL((k_emit<true, false>), grid, block, 0, st, xyz, lat, curve_off, attr,
+                         vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
+                         s->offsets);
+    else if (vattr)
+      hipLaunchKernelGGL((k_emit<false, true>), grid, block, 0, st, xyz, lat, curve_off, attr,
+                         vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
+                         s->offsets);
     else
-      hipLaunchKernelGGL((k_emit<false>), dim3(curve_blocks(C)), dim3(kBlock), 0, st, xyz, lat,
-                         curve_off, attr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
-                         rec.as<uint64_t>(),
-                         vox.as<uint32_t>(), rank.as<uint32_t>(), s->offsets);
+      hipLaunchKernelGGL((k_emit<false, false>), grid, block, 0, st, xyz, lat, curve_off, attr,
+                         vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
+                         rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
+                         s->offsets);
     LS_HIP(hipGetLastError());
   }
 
@@ -935,6 +978,8 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
 
   // 5. scatter + rank/gather into the set's record array
   if ((rc = ls_alloc(s, (void**)&s->records, sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
+  if (vattr && (rc = ls_alloc(s, (void**)&s->ends, sizeof(uint16_t) * (n_rec ? n_rec : 1))))
+    return rc;
   DeviceBuf idx(st);
   if ((rc = idx.alloc(sizeof(uint64_t) * (n_rec ? n_rec : 1)))) return rc;
   if (n_slots > 0) {
@@ -945,7 +990,8 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   }
   if (n_rec > 0) {
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(n_rec)), dim3(kBlock), 0, st, idx.as<uint64_t>(),
-                       rec.as<uint64_t>(), (int64_t)n_rec, s->offsets, s->records);
+                       rec.as<uint64_t>(), vattr ? ends_slots.as<uint16_t>() : nullptr,
+                       (int64_t)n_rec, s->offsets, s->records, vattr ? s->ends : nullptr);
     LS_HIP(hipGetLastError());
   }
 

@@ -107,3 +107,28 @@ def test_batch_rejects_invalid_view(sets):
     bad[4] = dict(bad[4], radius=-1.0)
     with pytest.raises(L.LinesetError):
         L.Batch([items[0], tuple(bad), items[2]])
+
+
+def test_every_autotuner_plan_equals_alone(sets):
+    """Each plan the autotuner can pick (tile shape x grid size) renders the
+    batch's views exactly as the plain renderer does."""
+    plans = L.batch_candidates()
+    assert len(plans) == 12 and len(set(plans)) == 12
+    items = _items(sets, 14, 9)
+    alone = [_alone(it) for it in items]
+    torch.cuda.synchronize()
+    for plan in plans:
+        for it in items:
+            it[3].fill_(-1.0)
+        b = L.Batch(items, plan=plan)
+        cfg = b.config()
+        assert (cfg["waves_x"], cfg["waves_y"]) == plan[:2] and cfg["autotuned"] == 0
+        b.render()
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            assert torch.equal(it[3], alone[k]), f"plan {plan}: view {k} differs"
+        b.close()
+    with pytest.raises(L.LinesetError):
+        L.Batch(items, plan=(3, 3, 1))
+    with pytest.raises(L.LinesetError):
+        L.Batch(items, plan=(2, 2, 0))

@@ -1,11 +1,15 @@
-"""GPU parity at the benchmark's full size: the scale workload (100k ABC-flow
+"""GPU parity at the benchmark's full sizes: the scale workload (100k ABC-flow
 streamlines x 200 vertices, 256^3 grid, 1920x1080 transparent perspective),
 in the launch configuration bench.py times. The CSR is compared in full;
 the density pyramid and illumination grids on sampled voxels; the frame on
 sampled pixels the oracle renders one by one (including the slowest tiles
 of the frame). At 1920x1080 the launch splits the core tiles over two
 workgroups; the same view at 3840x2160 is beyond the split limit and runs
-unsplit, so both launch forms of the transparent frame are checked."""
+unsplit, so both launch forms of the transparent frame are checked. The
+global-illumination workload (1M streamlines x 100 vertices, 512^3 grid,
+140M line records, AO + soft shadow, 1920x1080) is checked the same way:
+CSR in full, pyramid in full, grids on sampled voxels, the AO/shadow-shaded
+frame on sampled pixels."""
 import numpy as np
 import pytest
 import torch
@@ -100,3 +104,74 @@ def test_fullsize_frame_4k_unsplit_sampled_pixels(scale):
     pix = np.array(pix, dtype=np.int64)
     r, _ = O.render(ref, w["grid"], w["bins"], cam, pixels=pix, lut=lut, **params)
     U.assert_image_parity(img[pix], r, "fullsize 3840x2160 sampled pixels")
+
+
+# --- global-illumination workload: 1M x 100 vertices, 512^3, AO + shadow ----------------
+@pytest.fixture(scope="module")
+def gi():
+    w = dict(synth.WORKLOADS["gi"])
+    ls = synth.abc_lineset(w["n_curves"], w["n_vertices"], w["seed"], w["perturb"])
+    ref, _ = U.oracle_csr_from_xyz(ls, w["grid"], w["bins"])
+    s = L.lineset_voxelize(U.dev(ls.curve_off), w["grid"], w["bins"], xyz=U.dev(ls.xyz),
+                           attr=U.dev(ls.attr))
+    torch.cuda.synchronize()
+    return w, ls, ref, s
+
+
+def test_gi_csr_bit_exact(gi):
+    w, ls, ref, s = gi
+    offs, recs = U.gpu_csr(s)
+    print(f"[gi csr] records={len(recs)} oracle={len(ref.records)}", flush=True)
+    assert len(recs) > 100_000_000
+    assert np.array_equal(offs, ref.offsets)
+    assert np.array_equal(recs, ref.records)
+
+
+def test_gi_lod_illumination_and_frame(gi):
+    """Density pyramid in full (relative 1e-5), AO and shadow grids on 4000
+    sampled voxels against the oracle's cones (absolute 1e-5), and the
+    AO/shadow-shaded 1920x1080 frame on sampled pixels (the oracle fed its
+    own full AO and shadow grids)."""
+    w, ls, ref, s = gi
+    G = w["grid"]
+    lut = synth.lut_importance_alpha()
+    light = synth.LIGHT_DIR
+    L.lineset_build_lod(s, U.dev(lut), opaque=False, build_ao=True, build_shadow=True,
+                        light_dir=light)
+    torch.cuda.synchronize()
+    _, _, rho, _, _ = O.lod(ref, G, w["bins"], lut, opaque=False)
+    g_rho = L.lineset_export(s, L.EXPORT_LOD_RHO).cpu().numpy().astype(np.float64)
+    assert np.allclose(g_rho, rho, rtol=1e-5, atol=1e-12)
+    del g_rho
+    rng = np.random.default_rng(3)
+    vox = rng.integers(0, G ** 3, 4000)
+    gao = L.lineset_export(s, L.EXPORT_AO).cpu().numpy()
+    gsh = L.lineset_export(s, L.EXPORT_SHADOW).cpu().numpy()
+    dirs = O.fibonacci_dirs(16)
+    L64 = np.array(light, np.float32).astype(np.float64)
+    err_ao = err_sh = 0.0
+    for v in vox:
+        p = np.array([v % G, (v // G) % G, v // (G * G)], dtype=np.float64) + 0.5
+        ao = 1.0 - np.mean([O.cone(rho, G, p, d, 15.0) for d in dirs])
+        sh = 1.0 - O.cone(rho, G, p, L64, np.inf)
+        err_ao = max(err_ao, abs(gao[v] - ao))
+        err_sh = max(err_sh, abs(gsh[v] - sh))
+    print(f"[gi illum] sampled 4000 voxels: ao max_abs_err={err_ao:.3e} "
+          f"sh max_abs_err={err_sh:.3e}", flush=True)
+    assert err_ao < 1e-5 and err_sh < 1e-5
+    del gao, gsh
+    ao = O.ao_grid(rho, G, 16, 15.0, 1.0)
+    sh = O.shadow_grid(rho, G, L64)
+    cam = synth.default_camera((G,) * 3, w["width"], w["height"])
+    params = dict(radius=w["radius"], opaque=False, alpha_stop=0.95, merge_curves=True, shading=2,
+                  light_dir=light)
+    img = L.lineset_render(s, cam, U.dev(lut), **params)
+    torch.cuda.synchronize()
+    img = img.cpu().numpy().reshape(-1, 4)
+    W, H = cam.width, cam.height
+    pix = list(rng.integers(0, W * H, 3000))
+    # the densest part of the view: a 96 x 96 block around the image centre
+    pix += [(H // 2 - 48 + j) * W + W // 2 - 48 + i for j in range(0, 96, 4) for i in range(0, 96, 4)]
+    pix = np.array(pix, dtype=np.int64)
+    r, _ = O.render(ref, G, w["bins"], cam, pixels=pix, lut=lut, ao=ao, sh=sh, **params)
+    U.assert_image_parity(img[pix], r, "gi 1080p AO/shadow sampled pixels")
