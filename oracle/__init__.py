@@ -56,7 +56,8 @@ class ParamsS(C.Structure):
                 ("distance_alpha", C.c_int32), ("ao_mode", C.c_int32),
                 ("shadow_mode", C.c_int32), ("ao_rays", C.c_int32), ("ao_radius", C.c_float),
                 ("rep_level", C.c_int32), ("rho", C.POINTER(C.c_double)),
-                ("rep", C.POINTER(C.c_uint32)), ("ends", C.POINTER(C.c_uint16))]
+                ("rep", C.POINTER(C.c_uint32)), ("ends", C.POINTER(C.c_uint16)),
+                ("accel_depth", C.c_float), ("rgb", C.POINTER(C.c_double))]
 
 
 class CountersS(C.Structure):
@@ -194,6 +195,19 @@ def lod(csr: OracleCsr, grid, bins: int, lut, opaque: bool):
                  C.c_int32(bins), _p(lut, C.c_float), C.c_int32(int(opaque)),
                  _p(cnt, C.c_double), _p(ln, C.c_double), _p(rho, C.c_double))
     return cnt, ln, rho, dims, loff
+
+
+def lod_color(csr: OracleCsr, grid, bins: int, lut, opaque: bool) -> np.ndarray:
+    """Colour pyramid [level_off[-1], 3]: sum of length * sigma * lut rgb per
+    voxel, averaged up the levels like rho."""
+    g = _grid(grid)
+    dims, loff = lod_levels(g)
+    rgb = np.zeros((int(loff[-1]), 3))
+    lut = np.ascontiguousarray(lut, dtype=np.float32)
+    lib().or_lod_color(_p(csr.offsets, C.c_uint32), _p(csr.records, C.c_uint64), _p(g, C.c_int32),
+                       C.c_int32(bins), _p(lut, C.c_float), C.c_int32(int(opaque)),
+                       _p(rgb, C.c_double))
+    return rgb
 
 
 def cone(rho, grid, p, direction, s_max, aperture=1.0) -> float:
@@ -348,7 +362,7 @@ def decode(rec: int, bins: int):
 def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   lut=None, shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
                   light_dir=(0.0, 0.0, 1.0), distance_alpha=False, ao_mode=0, shadow_mode=0,
-                  ao_rays=16, ao_radius=15.0, rep_level=1):
+                  ao_rays=16, ao_radius=15.0, rep_level=1, accel_depth=0.0):
     p = ParamsS()
     p.radius = radius
     p.mode = mode
@@ -363,11 +377,12 @@ def params_struct(radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curve
     p.distance_alpha = int(distance_alpha)
     p.ao_mode, p.shadow_mode, p.ao_rays = int(ao_mode), int(shadow_mode), int(ao_rays)
     p.ao_radius, p.rep_level = float(ao_radius), int(rep_level)
+    p.accel_depth = float(accel_depth)
     return p, lut  # keep lut alive
 
 
 def render(csr: OracleCsr, grid, bins: int, cam, pixels=None, ao=None, sh=None,
-           threads: int = 0, rho=None, rep=None, **params):
+           threads: int = 0, rho=None, rep=None, rgb=None, **params):
     """fp64 image [H, W, 4] (or [n, 4] for a pixel list) plus counters dict.
     rho (density pyramid) and rep (representative lines) feed the
     per-fragment illumination sources of shading 2."""
@@ -380,6 +395,9 @@ def render(csr: OracleCsr, grid, bins: int, cam, pixels=None, ao=None, sh=None,
     if rep is not None:
         rep = np.ascontiguousarray(rep, dtype=np.uint32)
         p.rep = _p(rep, C.c_uint32)
+    if rgb is not None:
+        rgb = np.ascontiguousarray(rgb, dtype=np.float64)
+        p.rgb = _p(rgb, C.c_double)
     ends = getattr(csr, "ends", None)
     if ends is not None:
         ends = np.ascontiguousarray(ends, dtype=np.uint16)

@@ -68,6 +68,11 @@ int or_lod(const uint32_t* offsets, const uint64_t* records, const int32_t grid[
            int32_t bins, const float* lut_rgba, int32_t opaque,
            double* count, double* len, double* rho);
 
+/* Colour pyramid for opacity acceleration: rgb[v][3] = sum of length *
+ * sigma * lut colour over the voxel's lines, averaged up the levels. */
+int or_lod_color(const uint32_t* offsets, const uint64_t* records, const int32_t grid[3],
+                 int32_t bins, const float* lut_rgba, int32_t opaque, double* rgb);
+
 /* Sections "Shadow simulation" and "Ambient occlusion": per-voxel cone-traced
  * occlusion grids on the density pyramid. */
 double or_cone(const double* rho, const int32_t grid[3], const double p[3],
@@ -128,6 +133,8 @@ typedef struct {
   const uint32_t* rep;   /* representative lines, levels flat (shadow_mode 2) */
   const uint16_t* ends;  /* per-record endpoint attributes (or NULL): colour and
                             opacity from the attribute interpolated along the line */
+  float accel_depth;     /* opacity acceleration from this optical depth (0: off) */
+  const double* rgb;     /* colour pyramid [level_off][3] (or_lod_color), accel_depth > 0 */
 } or_params;
 
 typedef struct {
