@@ -393,7 +393,7 @@ def vdi_leg(L, synth, torch, dev, stream, s, cam, lut_op, lut_tr, light, reps=5)
     per-fragment sources, opaque and transparent, against the per-voxel
     grids."""
     L.lineset_build_lod(s, lut_tr, opaque=False, build_ao=True, build_shadow=True,
-                        light_dir=light, build_rep_lines=True, stream=stream)
+                        light_dir=light, build_rep_lines=True, build_color=True, stream=stream)
     out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)
     cases = {
@@ -418,8 +418,25 @@ def vdi_leg(L, synth, torch, dev, stream, s, cam, lut_op, lut_tr, light, reps=5)
                 e1.record(stream)
             stream.synchronize()
             res[f"{'opaque' if opaque else 'transparent'}_{name}_ms"] = e0.elapsed_time(e1) / reps
-    log(f"[bench] view-dependent illumination: {res}")
-    return {"workload": "scale set, 1920x1080 perspective, shading 2 sources", **res}
+    # opacity acceleration on the transparent frame (grid shading): time and
+    # the largest per-channel difference from the exact frame
+    p = dict(radius=0.4, opaque=False, alpha_stop=0.95, merge_curves=True, shading=2,
+             light_dir=light)
+    exact = L.lineset_render(s, cam, lut_tr, stream=stream, **p).clone()
+    for depth0 in (1.0, 2.0, 3.0):
+        with torch.cuda.stream(stream):
+            img = L.lineset_render(s, cam, lut_tr, out=out, stream=stream, accel_depth=depth0, **p)
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            for _ in range(reps):
+                L.lineset_render(s, cam, lut_tr, out=out, stream=stream, accel_depth=depth0, **p)
+            e1.record(stream)
+        stream.synchronize()
+        res[f"transparent_accel_depth{depth0:g}_ms"] = e0.elapsed_time(e1) / reps
+        res[f"transparent_accel_depth{depth0:g}_max_err"] = (img - exact).abs().max().item()
+    log(f"[bench] view-dependent illumination / acceleration: {res}")
+    return {"workload": "scale set, 1920x1080 perspective, shading 2 sources; opacity "
+                        "acceleration (error bound exp(-depth))", **res}
 
 
 def _lod_dims(grid):

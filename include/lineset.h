@@ -187,6 +187,11 @@ void lineset_destroy(ls_lineset_t set);
  * mean (a mean on a bin boundary to the upper bin). Level l + 1 averages the
  * joined lines of its children (x fastest, then y, z) in its own frame and
  * joins again. Exact integer arithmetic; bit-identical to the definition.
+ *
+ * Optionally a colour pyramid beside rho (LS_EXPORT_LOD_COLOR, float
+ * [level_off][3]): per voxel the sum over its lines of length * sigma * lut
+ * rgb, averaged up the levels like rho; rgb / rho is the density-weighted
+ * mean colour that opacity acceleration composites.
  * Errors: LS_EINVAL (bad cone count, radius, aperture or light), LS_ENOMEM;
  * LS_EUNSUPPORTED when a cone needs more than 48 samples or sample distances
  * not exact in fp32 (apertures far below 1). */
@@ -200,6 +205,7 @@ typedef struct {
   int32_t build_shadow;
   float light_dir[3];        /* unit vector towards a directional light */
   int32_t build_rep_lines;   /* 1: representative lines of every level (see below) */
+  int32_t build_color;       /* 1: colour pyramid for opacity acceleration (see below) */
 } ls_lod_desc;
 
 int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_stream);
@@ -250,9 +256,19 @@ int lineset_build_lod(ls_lineset_t set, const ls_lod_desc* desc, void* hip_strea
  * nothing; a tangent hit, l = 0, is transparent).
  *   lut_rgba   device, float [256][4] straight alpha
  *   rgba_out   device, float [height][width][4], premultiplied (C, A)
+ * Opacity acceleration (section "Transparency rendering", after Danskin and
+ * Hanrahan), transparent lines only: once the accumulated optical depth
+ * -ln(1 - A) reaches accel_depth > 0 after a fragment, the ray leaves the
+ * lines at the end of that voxel and samples the density pyramid instead:
+ * at optical depth d, level l = min(top, 1 + floor(log2(d / accel_depth))),
+ * step 2^l voxels, one trilinear sample at each step's midpoint with opacity
+ * min(1, rho 2^l) and the colour pyramid's mean colour (unlit), front to
+ * back until alpha_stop or the grid's edge. The image then differs from the
+ * exact one by at most exp(-accel_depth) per channel.
  * Errors: LS_EINVAL for a zero or negative size, radius <= 0 (or >= 1 in
  * mode 1), a zero forward/direction, shading 2 without the grids, pyramid or
- * representative lines its sources need, ao_rays outside [1, 256]. */
+ * representative lines its sources need, ao_rays outside [1, 256], a
+ * negative or non-finite accel_depth, acceleration without the pyramids. */
 typedef struct {
   float eye[3], forward[3], right[3], up[3];
   int32_t orthographic, width, height;
@@ -275,6 +291,7 @@ typedef struct {
   int32_t ao_rays;           /* ao_mode 1: rays per fragment (default 16) */
   float ao_radius;           /* ao_mode 1: radius of influence in voxels (default 15) */
   int32_t rep_level;         /* shadow_mode 2: pyramid level of the representative lines */
+  float accel_depth;         /* opacity acceleration from this optical depth (0: off; see above) */
 } ls_render_params;
 
 int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,
@@ -495,6 +512,7 @@ typedef struct {
   int32_t has_ao, has_shadow;
   int32_t has_rep_lines;
   int32_t has_vertex_attr;   /* per-line endpoint attributes (LS_EXPORT_ENDS) */
+  int32_t has_color;         /* colour pyramid (LS_EXPORT_LOD_COLOR) */
   int32_t level_dims[32][3];
   int64_t level_off[33];
   double lo_scale[4];        /* grid set-up of xyz input: lo[3], S */
@@ -512,7 +530,8 @@ enum {
   LS_EXPORT_AO = 5,          /* float [voxels] */
   LS_EXPORT_SHADOW = 6,      /* float [voxels] */
   LS_EXPORT_REP_LINES = 7,   /* uint32, all levels flat (level_off) */
-  LS_EXPORT_ENDS = 8         /* uint16 [n_records]: entry | exit << 8 attributes */
+  LS_EXPORT_ENDS = 8,        /* uint16 [n_records]: entry | exit << 8 attributes */
+  LS_EXPORT_LOD_COLOR = 9    /* float [level_off][3], all levels flat */
 };
 
 /* Copies one buffer of the set into `dst` (host or device). Errors:

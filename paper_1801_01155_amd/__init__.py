@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblineset.so")
 
 LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EUNSUPPORTED, LS_EBUSY, LS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 (EXPORT_OFFSETS, EXPORT_RECORDS, EXPORT_LOD_COUNT, EXPORT_LOD_LEN, EXPORT_LOD_RHO, EXPORT_AO,
- EXPORT_SHADOW, EXPORT_REP_LINES, EXPORT_ENDS) = range(9)
+ EXPORT_SHADOW, EXPORT_REP_LINES, EXPORT_ENDS, EXPORT_LOD_COLOR) = range(10)
 
 
 class LinesetError(RuntimeError):
@@ -39,7 +39,7 @@ class LodDesc(C.Structure):
     _fields_ = [("lut_rgba", C.c_void_p), ("opaque", C.c_int32), ("build_ao", C.c_int32),
                 ("ao_cones", C.c_int32), ("ao_radius", C.c_float), ("cone_aperture", C.c_float),
                 ("build_shadow", C.c_int32), ("light_dir", C.c_float * 3),
-                ("build_rep_lines", C.c_int32)]
+                ("build_rep_lines", C.c_int32), ("build_color", C.c_int32)]
 
 
 class CameraS(C.Structure):
@@ -55,7 +55,7 @@ class RenderParams(C.Structure):
                 ("shininess", C.c_float), ("light_dir", C.c_float * 3),
                 ("distance_alpha", C.c_int32), ("ao_mode", C.c_int32),
                 ("shadow_mode", C.c_int32), ("ao_rays", C.c_int32), ("ao_radius", C.c_float),
-                ("rep_level", C.c_int32)]
+                ("rep_level", C.c_int32), ("accel_depth", C.c_float)]
 
 
 class RenderCounters(C.Structure):
@@ -74,7 +74,7 @@ class Info(C.Structure):
                 ("n_record_slots", C.c_int64), ("nonempty_voxels", C.c_int64),
                 ("max_list", C.c_int64), ("n_levels", C.c_int32), ("has_ao", C.c_int32),
                 ("has_shadow", C.c_int32), ("has_rep_lines", C.c_int32),
-                ("has_vertex_attr", C.c_int32),
+                ("has_vertex_attr", C.c_int32), ("has_color", C.c_int32),
                 ("level_dims", (C.c_int32 * 3) * 32),
                 ("level_off", C.c_int64 * 33), ("lo_scale", C.c_double * 4),
                 ("device_bytes", C.c_size_t)]
@@ -243,7 +243,8 @@ def lineset_update(ls: LineSet, remove=None, curve_off=None, xyz=None, lattice=N
 
 def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=16,
                       ao_radius=15.0, cone_aperture=1.0, build_shadow=False,
-                      light_dir=(0.0, 0.0, 1.0), build_rep_lines=False, stream=None):
+                      light_dir=(0.0, 0.0, 1.0), build_rep_lines=False, build_color=False,
+                      stream=None):
     lut = _dev(lut, torch.float32)
     d = LodDesc()
     d.lut_rgba = lut.data_ptr()
@@ -255,6 +256,7 @@ def lineset_build_lod(ls: LineSet, lut, opaque=False, build_ao=False, ao_cones=1
     d.build_shadow = int(build_shadow)
     d.light_dir = (C.c_float * 3)(*light_dir)
     d.build_rep_lines = int(build_rep_lines)
+    d.build_color = int(build_color)
     _check(lib().lineset_build_lod(ls.handle, C.byref(d), _stream(stream)))
 
 
@@ -273,7 +275,7 @@ def camera_struct(cam) -> CameraS:
 def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_curves=True,
                   shading=1, ka=0.25, kd=0.75, ks=0.2, shininess=16.0,
                   light_dir=(0.0, 0.0, 1.0), distance_alpha=False, ao_mode=0, shadow_mode=0,
-                  ao_rays=16, ao_radius=15.0, rep_level=1) -> RenderParams:
+                  ao_rays=16, ao_radius=15.0, rep_level=1, accel_depth=0.0) -> RenderParams:
     p = RenderParams()
     p.radius = radius
     p.mode = mode
@@ -287,6 +289,7 @@ def render_params(lut, radius=0.4, mode=0, opaque=False, alpha_stop=0.95, merge_
     p.distance_alpha = int(distance_alpha)
     p.ao_mode, p.shadow_mode, p.ao_rays = int(ao_mode), int(shadow_mode), int(ao_rays)
     p.ao_radius, p.rep_level = float(ao_radius), int(rep_level)
+    p.accel_depth = float(accel_depth)
     return p
 
 
@@ -346,7 +349,7 @@ _EXPORT_DTYPE = {EXPORT_OFFSETS: torch.int32, EXPORT_RECORDS: torch.int64,
                  EXPORT_LOD_COUNT: torch.float32, EXPORT_LOD_LEN: torch.float32,
                  EXPORT_LOD_RHO: torch.float32, EXPORT_AO: torch.float32,
                  EXPORT_SHADOW: torch.float32, EXPORT_REP_LINES: torch.int32,
-                 EXPORT_ENDS: torch.int16}
+                 EXPORT_ENDS: torch.int16, EXPORT_LOD_COLOR: torch.float32}
 
 
 def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
@@ -360,7 +363,8 @@ def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
          EXPORT_LOD_RHO: i.level_off[i.n_levels] if i.n_levels else 0,
          EXPORT_AO: nvox, EXPORT_SHADOW: nvox,
          EXPORT_REP_LINES: i.level_off[i.n_levels] if i.has_rep_lines else 0,
-         EXPORT_ENDS: i.n_records if i.has_vertex_attr else 0}[what]
+         EXPORT_ENDS: i.n_records if i.has_vertex_attr else 0,
+         EXPORT_LOD_COLOR: 3 * i.level_off[i.n_levels] if i.has_color else 0}[what]
     t = torch.empty(max(int(n), 1), dtype=_EXPORT_DTYPE[what], device="cuda")
     _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
                                 _stream(stream)))

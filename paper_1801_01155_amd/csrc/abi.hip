@@ -126,7 +126,8 @@ int ls_alloc(ls_lineset* s, void** p, size_t bytes) {
 
 void ls_free_all(ls_lineset* s) {
   void* ptrs[] = {s->offsets, s->records, s->occupancy, s->lod_count, s->lod_len,
-                  s->lod_rho, s->ao,      s->sh,        s->cone_tab, s->rep, s->ends};
+                  s->lod_rho, s->ao,      s->sh,        s->cone_tab, s->rep, s->ends,
+                  s->lod_rgb};
   bool any = false;
   for (void* p : ptrs) any = any || p;
   // work queued on any stream may still read the set (hipFree would wait too)
@@ -136,7 +137,7 @@ void ls_free_all(ls_lineset* s) {
   s->records = nullptr;
   s->occupancy = nullptr;
   s->stats_pending = false;
-  s->lod_count = s->lod_len = s->lod_rho = s->ao = s->sh = nullptr;
+  s->lod_count = s->lod_len = s->lod_rho = s->ao = s->sh = s->lod_rgb = nullptr;
   s->cone_tab = nullptr;
   s->cone_tab_bytes = 0;
   s->rep = nullptr;
@@ -203,6 +204,15 @@ int check_render(const ls_lineset* s, const ls_camera* c, const ls_render_params
       ls_set_error("lineset_render: non-finite light_dir");
       return LS_EINVAL;
     }
+  }
+  if (!(p->accel_depth >= 0.f) || !std::isfinite(p->accel_depth)) {
+    ls_set_error("lineset_render: accel_depth must be finite and >= 0");
+    return LS_EINVAL;
+  }
+  if (p->accel_depth > 0.f && !p->opaque && (!s->lod_rho || !s->lod_rgb)) {
+    ls_set_error("lineset_render: opacity acceleration needs the density and colour pyramids "
+                 "(lineset_build_lod with build_color)");
+    return LS_EINVAL;
   }
   if (!aligned16(out) || !aligned16(p->lut_rgba)) {
     ls_set_error("lineset_render: rgba_out and lut_rgba must be 16-byte aligned");
@@ -371,6 +381,7 @@ int lineset_build_lod(ls_lineset_t s, const ls_lod_desc* d, void* hip_stream) {
   int rc;
   if ((rc = lod_build(s, d->lut_rgba, d->opaque, st))) return rc;
   if (d->build_rep_lines && (rc = rep_build(s, st))) return rc;
+  if (d->build_color && (rc = lod_color_build(s, d->lut_rgba, d->opaque, st))) return rc;
   if (d->build_ao && d->build_shadow) {
     bool applied = false;
     if ((rc = illum_ao_shadow(s, d->ao_cones, d->ao_radius, d->light_dir, d->cone_aperture, st,
@@ -467,6 +478,7 @@ int lineset_info(ls_lineset_t s, ls_info* o) {
   o->has_shadow = s->sh != nullptr;
   o->has_rep_lines = s->rep != nullptr;
   o->has_vertex_attr = s->ends != nullptr;
+  o->has_color = s->lod_rgb != nullptr;
   for (int l = 0; l < s->n_levels && l < 32; ++l)
     for (int a = 0; a < 3; ++a) o->level_dims[l][a] = s->level_dims[l][a];
   for (int l = 0; l <= s->n_levels && l < 33; ++l) o->level_off[l] = s->level_off[l];
@@ -492,6 +504,7 @@ int lineset_export(ls_lineset_t s, int32_t what, void* dst, size_t dst_bytes,
     case LS_EXPORT_LOD_RHO: src = s->lod_rho; bytes = lod_bytes; break;
     case LS_EXPORT_AO: src = s->ao; bytes = s->ao ? sizeof(float) * (size_t)s->nvox : 0; break;
     case LS_EXPORT_SHADOW: src = s->sh; bytes = s->sh ? sizeof(float) * (size_t)s->nvox : 0; break;
+    case LS_EXPORT_LOD_COLOR: src = s->lod_rgb; bytes = s->lod_rgb ? 3 * lod_bytes : 0; break;
     case LS_EXPORT_ENDS:
       src = s->ends;
       bytes = s->ends ? sizeof(uint16_t) * (size_t)s->n_records : 0;

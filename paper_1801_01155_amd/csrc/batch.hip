@@ -45,7 +45,7 @@ std::map<std::string, BatchPlan> g_plan_cache;
 // The extended kernel instance (see view_dependent in render_args.h).
 bool view_dependent_params(const ls_view& v) {
   return (v.params.shading == 2 && (v.params.ao_mode != 0 || v.params.shadow_mode != 0)) ||
-         (v.set && v.set->ends != nullptr);
+         (v.set && v.set->ends != nullptr) || (!v.params.opaque && v.params.accel_depth > 0.f);
 }
 
 std::string signature(const std::vector<ls_view>& v) {

@@ -202,7 +202,79 @@ __global__ __launch_bounds__(kBlock) void k_mip_brick(float* count, float* len, 
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Colour beside the density for opacity acceleration: per voxel the sum over
+// its lines of length * sigma * (transfer-function colour), three floats
+// interleaved; a thread per voxel walks its list.
+__global__ __launch_bounds__(kBlock) void k_lodc0(const uint32_t* offsets, const uint64_t* records,
+                                                  int64_t nvox, float inv_bins, const float* lut,
+                                                  int opaque, float* rgb) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= nvox) return;
+  float c[3] = {0.f, 0.f, 0.f};
+  for (uint32_t k = offsets[v]; k < offsets[v + 1]; ++k) {
+    const uint64_t rec = records[k];
+    float a[3], b[3];
+    decode_point((uint32_t)(rec & 0x7FFFu), inv_bins, a);
+    decode_point((uint32_t)((rec >> 15) & 0x7FFFu), inv_bins, b);
+    const float dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    const float L = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float* l = lut + 4 * ((rec >> 32) & 0xFF);
+    const float w = L * (opaque ? 1.f : l[3]);
+    c[0] += w * l[0];
+    c[1] += w * l[1];
+    c[2] += w * l[2];
+  }
+  rgb[3 * v + 0] = c[0];
+  rgb[3 * v + 1] = c[1];
+  rgb[3 * v + 2] = c[2];
+}
+
+// One coarser colour level: a thread per parent averages its 8 children
+// (x fastest, missing children beyond an odd side count as 0).
+__global__ __launch_bounds__(kBlock) void k_mipc(const float* child, float* parent, MipArgs m) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t np = (int64_t)m.px * m.py * m.pz;
+  if (v >= np) return;
+  const int32_t x = (int32_t)(v % m.px), y = (int32_t)((v / m.px) % m.py),
+                z = (int32_t)(v / ((int64_t)m.px * m.py));
+  float s[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < 8; ++k) {
+    const int32_t cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+    if (cx >= m.cx || cy >= m.cy || cz >= m.cz) continue;
+    const int64_t ci = cx + (int64_t)m.cx * (cy + (int64_t)m.cy * cz);
+    s[0] += child[3 * ci + 0];
+    s[1] += child[3 * ci + 1];
+    s[2] += child[3 * ci + 2];
+  }
+  parent[3 * v + 0] = s[0] * 0.125f;
+  parent[3 * v + 1] = s[1] * 0.125f;
+  parent[3 * v + 2] = s[2] * 0.125f;
+}
+
 }  // namespace
+
+int lod_color_build(ls_lineset* s, const float* lut, int opaque, hipStream_t st) {
+  int rc;
+  if (!s->lod_rgb) {
+    if ((rc = ls_alloc(s, (void**)&s->lod_rgb,
+                       3 * sizeof(float) * (size_t)s->level_off[s->n_levels])))
+      return rc;
+  }
+  if (s->nvox > 0) {
+    hipLaunchKernelGGL(k_lodc0, dim3(blocks_for(s->nvox)), dim3(kBlock), 0, st, s->offsets,
+                       s->records, s->nvox, 1.0f / (float)s->bins, lut, opaque, s->lod_rgb);
+    LS_HIP(hipGetLastError());
+  }
+  for (int L = 0; L + 1 < s->n_levels; ++L) {
+    const int64_t n = s->level_off[L + 2] - s->level_off[L + 1];
+    MipArgs m{s->level_dims[L][0],     s->level_dims[L][1],     s->level_dims[L][2],
+              s->level_dims[L + 1][0], s->level_dims[L + 1][1], s->level_dims[L + 1][2]};
+    hipLaunchKernelGGL(k_mipc, dim3(blocks_for(n)), dim3(kBlock), 0, st,
+                       s->lod_rgb + 3 * s->level_off[L], s->lod_rgb + 3 * s->level_off[L + 1], m);
+    LS_HIP(hipGetLastError());
+  }
+  return LS_OK;
+}
 
 void lod_plan(const int32_t grid[3], int32_t* n_levels, int32_t dims[][3], int64_t* level_off) {
   int n = 0;

@@ -49,6 +49,7 @@ struct ls_lineset {
   float* lod_count;
   float* lod_len;
   float* lod_rho;
+  float* lod_rgb;         // colour pyramid [level_off][3] (opacity acceleration), or null
   float* ao;
   float* sh;
   uint32_t* rep;          // representative lines, levels flat at level_off (or null)
@@ -103,6 +104,8 @@ int vox_occupancy(ls_lineset* s, hipStream_t st);
 // Density pyramid and illumination (lod.hip, illum.hip).
 void lod_plan(const int32_t grid[3], int32_t* n_levels, int32_t dims[][3], int64_t* level_off);
 int lod_build(ls_lineset* s, const float* lut, int opaque, hipStream_t st);
+// Colour pyramid beside rho (after lod_build): sum of length * sigma * rgb.
+int lod_color_build(ls_lineset* s, const float* lut, int opaque, hipStream_t st);
 int illum_ao(ls_lineset* s, int n_cones, float radius, float aperture, hipStream_t st);
 // Both grids in one pass of the column cone tracer (the shadow cone rides
 // along with the AO cones) when the schedules allow it; *applied = false

@@ -224,6 +224,7 @@ struct Accum {
   float C[3] = {0.f, 0.f, 0.f};
   float A = 0.f;
   bool done = false;
+  bool switched = false;   // opacity acceleration: leave the lines for the pyramid
   MergeLds mt;
   __device__ Accum(const MergeLds& m) : mt(m) {
 #pragma unroll
@@ -482,6 +483,36 @@ __device__ inline bool rep_shadow(const RenderArgs& R, const int32_t cell[3], co
   return false;
 }
 
+// Colour pyramid sample (three interleaved floats per cell), as sample_level.
+__device__ inline void sample_level3(const float* lev, const int32_t dim[3], int lv,
+                                     const int32_t cell[3], const float q[3], float out[3]) {
+  #pragma clang fp contract(fast)
+  const float scale = __builtin_ldexpf(1.0f, -lv);
+  const int32_t mask = (1 << lv) - 1;
+  int32_t i0[3], i1[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = ((float)(cell[a] & mask) + q[a]) * scale - 0.5f;
+    const float fl = floorf(x);
+    f[a] = x - fl;
+    const int32_t lo = (cell[a] >> lv) + (int32_t)fl;
+    i0[a] = min(max(lo, 0), dim[a] - 1);
+    i1[a] = min(max(lo + 1, 0), dim[a] - 1);
+  }
+  const int64_t sy = dim[0], sz = (int64_t)dim[0] * dim[1];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+    const float w = (bx ? f[0] : 1.f - f[0]) * (by ? f[1] : 1.f - f[1]) * (bz ? f[2] : 1.f - f[2]);
+    const int64_t i = (bx ? i1[0] : i0[0]) + (by ? i1[1] : i0[1]) * sy + (bz ? i1[2] : i0[2]) * sz;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] += w * lev[3 * i + c];
+  }
+}
+
 // Shade and composite one fragment. p is the entry point in the frame of
 // `cell`, a/b the record's endpoints in the same frame, dt the ray-parameter
 // length of the hit (exit - entry).
@@ -552,7 +583,12 @@ __device__ __attribute__((always_inline)) inline void composite(const RenderArgs
   acc.C[2] += w * col[2];
   acc.A += w;
   cnt.fragments++;
-  if (acc.A >= R.alpha_stop) acc.done = true;
+  if (acc.A >= R.alpha_stop) {
+    acc.done = true;
+  } else if (kVdi && acc.A >= R.accel_A0) {
+    acc.done = true;
+    acc.switched = true;
+  }
 }
 
 // Sorted register buffer of hits. Key (t, idx) lexicographic.
@@ -625,6 +661,58 @@ struct Ray {
   double t0;
   bool alive;
 };
+
+// Opacity acceleration (section "Transparency rendering", after Danskin and
+// Hanrahan): from the ray parameter t0 (the end of the voxel where the
+// optical depth passed accel_depth) the ray samples the density pyramid, at
+// depth d on level min(top, 1 + floor(log2(d / accel_depth))) with step
+// D = 2^level voxels, one trilinear sample per step at its midpoint: opacity
+// min(1, rho D), colour the colour pyramid's mean (unlit); front to back until
+// alpha_stop or the grid's edge.
+__device__ inline void accel_phase(const RenderArgs& R, const Ray& ray, double t0, Accum& acc) {
+  const double dx = ray.d[0], dy = ray.d[1], dz = ray.d[2];
+  const double dl = sqrt(dx * dx + dy * dy + dz * dz);
+  const double u[3] = {dx / dl, dy / dl, dz / dl};
+  double s = t0 * dl;
+  const int top = R.n_levels - 1;
+  for (int it = 0; it < 4096 && acc.A < R.alpha_stop; ++it) {
+    const double delta = -log(1.0 - (double)acc.A);
+    int lv = 1 + (int)floor(log2(delta / (double)R.accel_depth));
+    lv = lv < 1 ? 1 : lv;
+    lv = lv > top ? top : lv;
+    const double D = ldexp(1.0, lv);
+    double x[3];
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      x[a] = ray.od[a] + (s + 0.5 * D) * u[a];
+      inside &= x[a] >= 0.0 && x[a] < (double)R.g[a];
+    }
+    if (!inside) break;
+    int32_t dim[3], cell[3];
+    int64_t off;
+    level_geom(R.g, lv, dim, off);
+    float q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double fl = floor(x[a]);
+      cell[a] = (int32_t)fl;
+      q[a] = (float)(x[a] - fl);
+    }
+    const float r = sample_level(R.rho + off, dim, lv, cell, q);
+    const float alpha = fminf(r * (float)D, 1.f);
+    if (r > 0.f && alpha > 0.f) {
+      float c[3];
+      sample_level3(R.rgb + 3 * off, dim, lv, cell, q, c);
+      const float w = (1.f - acc.A) * alpha, ir = 1.f / r;
+      acc.C[0] += w * (c[0] * ir);
+      acc.C[1] += w * (c[1] * ir);
+      acc.C[2] += w * (c[2] * ir);
+      acc.A += w;
+    }
+    s += D;
+  }
+}
 
 __device__ inline void make_ray(const RenderArgs& R, int i, int j, float o[3], float d[3]) {
   double u = __dadd_rn(__ddiv_rn(__dmul_rn(2.0, __dadd_rn((double)i, 0.5)), (double)R.W), -1.0);
@@ -1242,6 +1330,7 @@ __device__ __attribute__((always_inline)) inline void render_pixel(const RenderA
       }
     }
   }
+  if (kVdi && acc.switched && valid) accel_phase(R, ray, ray.t0, acc);
   if (cnt.live_evictions != live_ev0) cnt.overflow_rays++;
   if (valid) {
     float4 px = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
@@ -1468,6 +1557,10 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.rho = s->lod_rho;
   R.rep = s->rep;
   R.ends = s->ends;
+  R.accel_depth = p->accel_depth;
+  R.accel_A0 = (!p->opaque && p->accel_depth > 0.f) ? (float)(1.0 - std::exp(-(double)p->accel_depth))
+                                                    : 2.f;
+  R.rgb = s->lod_rgb;
   R.out = out;
   R.counters = dev_counters;
   R.wx = wx;

@@ -30,6 +30,9 @@ struct RenderArgs {
   const float* rho;               // density pyramid, levels flat
   const uint32_t* rep;            // representative lines, levels flat
   const uint16_t* ends;           // per-record endpoint attributes (or null)
+  // opacity acceleration: switch at A >= accel_A0 (2: off), depth scale
+  float accel_A0, accel_depth;
+  const float* rgb;               // colour pyramid, levels flat, 3 floats per cell
   float* out;
   RenderCounters* counters;
   int32_t wx, wy;                 // tile = wx x wy waves of 8 x 8 pixels
@@ -62,7 +65,8 @@ int launch_render(const RenderArgs& R, hipStream_t st);
 // pyramid or the representative lines per fragment (view-dependent
 // illumination), or its set carries per-line endpoint attributes.
 inline bool view_dependent(const RenderArgs& R) {
-  return (R.shading == 2 && (R.ao_mode != 0 || R.shadow_mode != 0)) || R.ends != nullptr;
+  return (R.shading == 2 && (R.ao_mode != 0 || R.shadow_mode != 0)) || R.ends != nullptr ||
+         R.accel_A0 <= 1.f;
 }
 BatchQueues make_queues(int total_tiles);
 // dev_queue: 8 queue counters (zeroed before the launch), followed by a
