@@ -30,6 +30,12 @@
 //     premultiplied front-to-back compositing, termination at alpha_stop.
 #include "render_args.h"
 
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -1360,6 +1366,7 @@ __device__ inline void load_lut(const RenderArgs& R, float4* lut_lds) {
 
 template <int kMode, bool kCount, bool kVdi>
 __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
+  const unsigned long long t_start = R.times ? wall_clock64() : 0ull;
   int b = blockIdx.x;
   int tile;
   bool live;
@@ -1380,6 +1387,11 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
         b -= ns - R.split_n;
       }
     }
+    if (R.order) {
+      // tiles by decreasing estimated cost
+      tile = R.order[b];
+      live = tile >= 0 && tile < R.n_tiles;
+    } else {
     // Tiles in square rings around the projection of the grid centre, where
     // rays cross the most voxels: the costliest tiles start first instead of
     // setting the frame's tail. Ring r holds workgroups [(2r-1)^2, (2r+1)^2).
@@ -1408,6 +1420,7 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
     const int tiles_y = R.n_tiles / R.tiles_x;
     live = tx >= 0 && ty >= 0 && tx < R.tiles_x && ty < tiles_y;
     tile = ty * R.tiles_x + tx;
+    }
   } else {
     // Workgroup b runs on XCD b % 8. XCD x renders the tile rows x, x + 8,
     // x + 16, ...: whole rows keep neighbouring tiles in one L2, and every
@@ -1444,6 +1457,10 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
     render_pixel<kMode, kVdi>(R, lut_lds, merge_lds, i, j, valid && i < R.W && j < R.H, cnt);
   }
   if (kCount) flush_counts(R.counters, cnt);
+  if (R.times && threadIdx.x == 0) {
+    const unsigned long long dt = wall_clock64() - t_start;
+    atomicAdd(R.times + tile, dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu);
+  }
 }
 
 // Persistent batched renderer: one launch renders the tiles of many views.
@@ -1511,6 +1528,88 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
   if (kCount && counters) flush_counts(reinterpret_cast<RenderCounters*>(counters + kXcds), cnt);
 }
 
+// ---------------------------------------------------------------------------
+// Launch order by measured cost. A frame lasts as long as its slowest
+// workgroups, and the costly tiles are wherever the line set is dense along
+// the view (not necessarily the middle of the image, where the ring order
+// starts). Every workgroup adds its duration to its tile's time; when the
+// same view is rendered again on the same stream, the tiles are bucketed by
+// that time, eight buckets per octave (k_tile_hist), and launched by
+// decreasing bucket (k_tile_order), so the longest start first and are the
+// ones split.
+constexpr int kCostBuckets = 256;
+
+__device__ inline int cost_bucket(uint32_t c) {
+  if (c == 0u) return 0;
+  const int lz = 31 - __builtin_clz(c);
+  const int frac = lz >= 3 ? (int)((c >> (lz - 3)) & 7u) : (int)((c << (3 - lz)) & 7u);
+  return min(kCostBuckets - 1, 1 + 8 * lz + frac);
+}
+
+// Buckets of the tiles' times (kept, so the order pass sees the same ones)
+// and their histogram.
+__global__ __launch_bounds__(kBlock) void k_tile_hist(const uint32_t* __restrict__ cost,
+                                                      int32_t n_tiles,
+                                                      uint8_t* __restrict__ bucket,
+                                                      uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kCostBuckets];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < n_tiles) {
+    const int q = cost_bucket(cost[t]);
+    bucket[t] = (uint8_t)q;
+    atomicAdd(h + q, 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(hist + threadIdx.x, h[threadIdx.x]);
+}
+
+// order[p]: the tile at position p, by decreasing bucket (the order inside a
+// bucket depends on atomic order; every tile appears once). Clears the
+// times for the frame about to be measured.
+__global__ __launch_bounds__(kBlock) void k_tile_order(uint32_t* __restrict__ cost,
+                                                       const uint8_t* __restrict__ bucket,
+                                                       int32_t n_tiles,
+                                                       const uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ cursor,
+                                                       int32_t* __restrict__ order) {
+  static_assert(kBlock == kCostBuckets, "one thread per bucket");
+  __shared__ uint32_t pre[kCostBuckets];   // tiles in higher buckets
+  __shared__ uint32_t cnt[kCostBuckets];
+  __shared__ uint32_t base[kCostBuckets];
+  const int b = threadIdx.x;
+  // suffix sum of the histogram (exclusive), by a block scan
+  uint32_t x = hist[kCostBuckets - 1 - b];
+  pre[b] = x;
+  cnt[b] = 0u;
+  __syncthreads();
+  for (int d = 1; d < kCostBuckets; d <<= 1) {
+    const uint32_t y = b >= d ? pre[b - d] : 0u;
+    __syncthreads();
+    pre[b] += y;
+    __syncthreads();
+  }
+  // pre[k] = sum of hist[255 - k .. 255] (inclusive); bucket q's start is
+  // the sum over buckets above it = pre[254 - q] for q < 255, 0 for q = 255
+  const uint32_t start = b == kCostBuckets - 1 ? 0u : pre[kCostBuckets - 2 - b];
+  __syncthreads();
+  base[b] = start;
+  __syncthreads();
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  int q = 0;
+  uint32_t r = 0;
+  if (t < n_tiles) {
+    q = bucket[t];
+    cost[t] = 0u;
+    r = atomicAdd(cnt + q, 1u);
+  }
+  __syncthreads();
+  if (cnt[b]) base[b] += atomicAdd(cursor + b, cnt[b]);
+  __syncthreads();
+  if (t < n_tiles) order[base[q] + r] = t;
+}
+
 }  // namespace
 
 int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
@@ -1570,6 +1669,7 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.n_tiles = R.tiles_x * tiles_y;
   R.tiles_per_xcd = (R.n_tiles + kXcds - 1) / kXcds;
   R.spiral_r = -1;
+  R.order = nullptr;
   R.split_n = 0;
   R.split_s = 1;
   {
@@ -1631,9 +1731,10 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
 int launch_render(const RenderArgs& R, hipStream_t st) {
   const int tiles_y = R.n_tiles / R.tiles_x;
   const unsigned blocks =
-      R.spiral_r >= 0 ? (unsigned)((2 * R.spiral_r + 1) * (2 * R.spiral_r + 1) +
-                                   R.split_n * (R.split_s - 1))
-                      : (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
+      R.order ? (unsigned)(R.n_tiles + R.split_n * (R.split_s - 1))
+      : R.spiral_r >= 0 ? (unsigned)((2 * R.spiral_r + 1) * (2 * R.spiral_r + 1) +
+                                     R.split_n * (R.split_s - 1))
+                        : (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
   const unsigned threads = (unsigned)(64 * R.wx * R.wy);
   const size_t lds = merge_lds_bytes(threads);
   const dim3 grid(blocks), block(threads);
@@ -1661,10 +1762,150 @@ int launch_render(const RenderArgs& R, hipStream_t st) {
   return LS_OK;
 }
 
+namespace {
+
+// Launch-order state per (device, stream): the tile times of the stream's
+// last kOrderViews distinct views (least recently used replaced), and one
+// work buffer (bucket counters, per-tile buckets, the order). Work queued on
+// one stream runs in order, so its frames share these buffers. A buffer that
+// must grow is replaced after synchronising the stream; all are kept until
+// the process ends.
+constexpr int kOrderViews = 64;
+
+struct OrderKey {
+  int32_t grid[3];
+  int64_t n_records;
+  ls_camera cam;
+  ls_render_params params;
+  int32_t split;
+};
+
+struct ViewTimes {
+  OrderKey key;
+  void* times = nullptr;
+  size_t bytes = 0;
+  uint64_t used = 0;
+};
+
+struct StreamOrder {
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  std::vector<ViewTimes> views;
+  uint64_t clock = 0;
+};
+
+std::mutex g_order_mu;
+std::map<std::pair<int, hipStream_t>, StreamOrder> g_order;
+
+// Replaces *p (after synchronising st) by a block of at least `bytes`.
+int grow(void** p, size_t* have, size_t bytes, hipStream_t st) {
+  if (*have >= bytes) return LS_OK;
+  if (*p) {
+    LS_HIP(hipStreamSynchronize(st));
+    pool_free(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  return pool_alloc(bytes, p, have);
+}
+
+// Workgroups the plain launch keeps resident on the device at once.
+int resident_blocks(int* out) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  LS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it == cache.end()) {
+    hipDeviceProp_t prop;
+    LS_HIP(hipGetDeviceProperties(&prop, dev));
+    int per_cu = 0;
+    LS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(k_render<0, false, false>), kWave,
+        merge_lds_bytes(kWave)));
+    it = cache.emplace(dev, prop.multiProcessorCount * (per_cu > 0 ? per_cu : 1)).first;
+  }
+  *out = it->second;
+  return LS_OK;
+}
+
+// Transparent plain frames with more workgroups than the device holds at
+// once: tile times are measured, and a frame of a view the stream rendered
+// before (same set shape, image, camera and parameters) is launched in the
+// order of its last times. (Opaque rays end at the first surface: the ring
+// order already starts the costly tiles early there.)
+int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p,
+               RenderArgs& R, hipStream_t st) {
+  if (R.opaque) return LS_OK;
+  int resident = 0, rc;
+  if ((rc = resident_blocks(&resident))) return rc;
+  if ((int64_t)R.n_tiles + (int64_t)R.split_n * (R.split_s - 1) <= resident) return LS_OK;
+  OrderKey key;
+  std::memset(&key, 0, sizeof(key));
+  for (int a = 0; a < 3; ++a) key.grid[a] = s->grid[a];
+  key.n_records = s->n_records;
+  key.cam = *cam;
+  key.params = *p;
+  key.split = R.split_n * 8 + R.split_s;
+  int dev = 0;
+  LS_HIP(hipGetDevice(&dev));
+  const int64_t n = R.n_tiles;
+  std::lock_guard<std::mutex> lk(g_order_mu);
+  StreamOrder& so = g_order[{dev, st}];
+  ++so.clock;
+  int v = -1;
+  for (int k = 0; k < (int)so.views.size(); ++k)
+    if (std::memcmp(&so.views[k].key, &key, sizeof(key)) == 0) v = k;
+  bool repeat = v >= 0;
+  if (!repeat) {
+    if ((int)so.views.size() < kOrderViews) {
+      so.views.emplace_back();
+      v = (int)so.views.size() - 1;
+    } else {
+      v = 0;
+      for (int k = 1; k < kOrderViews; ++k)
+        if (so.views[k].used < so.views[v].used) v = k;
+    }
+    so.views[v].key = key;
+  }
+  ViewTimes& vt = so.views[v];
+  vt.used = so.clock;
+  if (vt.bytes < sizeof(uint32_t) * n) repeat = false;
+  if ((rc = grow(&vt.times, &vt.bytes, sizeof(uint32_t) * n, st))) return rc;
+  // work: hist, cursor, order (int32 per tile), bucket (uint8 per tile)
+  if ((rc = grow(&so.work, &so.work_bytes,
+                 sizeof(uint32_t) * (2 * kCostBuckets + n) + (size_t)n, st)))
+    return rc;
+  uint32_t* times = static_cast<uint32_t*>(vt.times);
+  uint32_t* hist = static_cast<uint32_t*>(so.work);
+  uint32_t* cursor = hist + kCostBuckets;
+  int32_t* order = reinterpret_cast<int32_t*>(cursor + kCostBuckets);
+  uint8_t* bucket = reinterpret_cast<uint8_t*>(order + n);
+  if (repeat) {
+    if ((rc = fill_u32(hist, 0u, 2 * kCostBuckets, st))) return rc;
+    const unsigned tb = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_tile_hist, dim3(tb), dim3(kBlock), 0, st, times, (int32_t)n, bucket,
+                       hist);
+    hipLaunchKernelGGL(k_tile_order, dim3(tb), dim3(kBlock), 0, st, times, bucket, (int32_t)n,
+                       hist, cursor, order);
+    LS_HIP(hipGetLastError());
+    R.order = order;
+  } else {
+    if ((rc = fill_u32(times, 0u, n, st))) return rc;
+  }
+  R.times = times;
+  return LS_OK;
+}
+
+}  // namespace
+
 int render_frame(const ls_lineset* s, const ls_camera* cam, const ls_render_params* p, float* out,
                  RenderCounters* dev_counters, hipStream_t st) {
   RenderArgs R;
   make_render_args(s, cam, p, out, 1, 1, dev_counters, &R);
+  int rc;
+  if (R.spiral_r >= 0 && (rc = tile_order(s, cam, p, R, st))) return rc;
   return launch_render(R, st);
 }
 

@@ -45,6 +45,11 @@ struct RenderArgs {
   // are rendered by split_s workgroups each, on 8 / split_s pixel rows, so
   // the waves over the densest part of the image hold fewer rays
   int32_t split_n, split_s;
+  // plain launch order by measured cost (tile_order): workgroup position p
+  // renders tile order[p]; null: the ring order above. times (or null):
+  // each workgroup adds its duration (10 ns ticks) to its tile's entry
+  const int32_t* order;
+  uint32_t* times;
 };
 
 // Tile queues of the persistent kernel: one contiguous range per XCD.

@@ -163,6 +163,38 @@ def test_deterministic_frames(medium):
     assert torch.equal(a, b)
 
 
+def test_repeated_views_in_measured_order(medium):
+    """Transparent frames with more tiles than the device holds at once: from
+    a view's second frame on a stream, its tiles are launched in the order of
+    their measured times (longest first). Every frame must equal the view's
+    first one (ring order) bit for bit: two views interleaved, on the default
+    stream and on a stream of their own, output cleared to NaN before each
+    frame so that a tile left out would show."""
+    ls, ref, s = medium
+    lut = U.dev(synth.lut_importance_alpha())
+    cams = [synth.default_camera((96,) * 3, 640, 480),
+            synth.orbit_cameras((96,) * 3, 1, 31, 600, 520)[0]]
+    kw = dict(radius=0.4, opaque=False, shading=1)
+    first = [L.lineset_render(s, c, lut, **kw).clone() for c in cams]
+    torch.cuda.synchronize()
+    for f in first:
+        assert float(f[..., 3].mean()) > 0.02
+    side = torch.cuda.Stream()
+    for st in (None, side):
+        for rep in range(3):
+            for c, f in zip(cams, first):
+                out = torch.full((c.height, c.width, 4), float("nan"), device="cuda")
+                if st is not None:
+                    st.wait_stream(torch.cuda.current_stream())
+                    with torch.cuda.stream(st):
+                        L.lineset_render(s, c, lut, out=out, stream=st, **kw)
+                    st.synchronize()
+                else:
+                    L.lineset_render(s, c, lut, out=out, **kw)
+                    torch.cuda.synchronize()
+                assert torch.equal(out, f), f"view {c.width}x{c.height} frame {rep + 1}"
+
+
 # --- bounded merge table -----------------------------------------------------------------
 def _bundle_along_z(n, grid=16):
     """n straight lines along z (the view direction below) through a bundle of
