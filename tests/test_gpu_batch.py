@@ -71,6 +71,26 @@ def test_batch_equals_alone(sets, autotune, graph):
     b.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_repeated_launches_equal_alone(sets, graph):
+    """Every launch of a batch (eager or graph replay) gives each view's
+    image: outputs cleared to NaN before each of four launches, so that a
+    tile left out would show."""
+    items = _items(sets, 24, 11 + int(graph))
+    b = L.Batch(items, autotune=False, graph=graph)
+    print(f"[batch] config={b.config()}", flush=True)
+    refs = [_alone(it).clone() for it in items]
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for it in items:
+            it[3].fill_(float("nan"))
+        b.render()
+        torch.cuda.synchronize()
+        for k, (it, ref) in enumerate(zip(items, refs)):
+            assert torch.equal(it[3], ref), f"launch {rep + 1} view {k}"
+    b.close()
+
+
 def test_batch_view_matches_oracle(sets):
     ls, grid, s = sets[1]
     ref, _ = U.oracle_csr_from_xyz(ls, grid, 32)
