@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -282,6 +283,7 @@ struct Last {
   unsigned attr;   // vertex attribute interpolated to the event (attribute input)
 };
 
+template <bool kAttr>
 __device__ inline Last shfl_last(const Last& v, int src) {
   Last o;
   o.has = __shfl(v.has, src, 64);
@@ -290,7 +292,7 @@ __device__ inline Last shfl_last(const Last& v, int src) {
   o.xn2 = __shfl(v.xn2, src, 64);
   o.den = __shfl(v.den, src, 64);
   o.entry = __shfl(v.entry, src, 64);
-  o.attr = __shfl(v.attr, src, 64);
+  o.attr = kAttr ? __shfl(v.attr, src, 64) : 0u;
   return o;
 }
 
@@ -307,6 +309,8 @@ __device__ inline unsigned event_attr(unsigned a0, unsigned a1, long long num, l
 // (exact cross-multiplied comparison; on a tie the lowest axis, the face the
 // walk in for_each_event gives a simultaneous event), and it enters the
 // segment's final voxel.
+// (kAttr: also the vertex attribute a0 -> a1 interpolated to that event.)
+template <bool kAttr>
 __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
                                       const GridArgs& ga, Last& out, unsigned a0 = 0,
                                       unsigned a1 = 0) {
@@ -353,7 +357,7 @@ __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
 #pragma unroll
   for (int b = 0; b < 3; ++b) xl[b] = (uint32_t)xn[b];
   out.entry = face_code(fa, df > 0 ? 0 : 1, xl, (int32_t)den, c1, ga);
-  out.attr = event_attr(a0, a1, nf, den);
+  out.attr = kAttr ? event_attr(a0, a1, nf, den) : 0u;
   return cross;
 }
 
@@ -370,7 +374,10 @@ struct EmitRing {
   uint32_t entry[kEmitRing];
   int32_t den[kEmitRing];
   long long x[3][kEmitRing];
-  uint32_t va[kEmitRing];   // attribute input: a0 | a1 << 8 | (event before) << 16
+};
+
+struct EmitRingAttr : EmitRing {
+  uint32_t va[kEmitRing];   // a0 | a1 << 8 | (attribute at the event before) << 16
 };
 
 // Lines of every curve in curve order: the line inside a voxel runs from
@@ -392,12 +399,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
                                                  uint64_t* rec_out, uint16_t* ends_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
                                                  uint32_t* hist) {
-  __shared__ EmitRing rings[kWavesPerBlock];
+  using Ring = std::conditional_t<kAttr, EmitRingAttr, EmitRing>;
+  __shared__ Ring rings[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const SnapArgs sa = kFloatIn ? *sap : SnapArgs{};
   const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (c >= n_curves) return;  // wave-uniform
-  EmitRing& Q = rings[threadIdx.x >> 6];
+  Ring& Q = rings[threadIdx.x >> 6];
   const int64_t v0 = curve_off[c], v1 = curve_off[c + 1];
   const uint64_t w0 = slot_off[c], w_end = slot_off[c + 1];
   const uint64_t hi_bits =
@@ -420,7 +428,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     uint64_t g = Q.g[k];
     bool has_prev = bden != 0, first = true;
     uint32_t prev_entry = Q.entry[k];
-    const uint32_t va = kAttr ? Q.va[k] : 0u;
+    uint32_t va = 0u;
+    if constexpr (kAttr) va = Q.va[k];
     uint32_t prev_attr = va >> 16;
     for_each_event<true>(P0, P1, ga, [&](const Ev& ev, const int32_t* cell) {
       const uint32_t ea = kAttr ? event_attr(va & 0xFFu, (va >> 8) & 0xFFu, ev.nf, ev.den) : 0u;
@@ -477,7 +486,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     Last mine{0, 0, 0, 0, 1, 0u, 0u};
     uint32_t a01 = 0;
     if (kAttr && valid) a01 = (uint32_t)vattr[i] | ((uint32_t)vattr[i + 1] << 8);
-    if (valid) e = last_event(P0, P1, ga, mine, a01 & 0xFFu, a01 >> 8);
+    if (valid) e = last_event<kAttr>(P0, P1, ga, mine, a01 & 0xFFu, a01 >> 8);
     // exclusive prefix sum of the crossing counts
     uint32_t inc = e;
 #pragma unroll
@@ -497,7 +506,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
     }
     int prev_src = __shfl_up(src, 1, 64);
     if (lane == 0) prev_src = -1;
-    Last before = shfl_last(mine, prev_src >= 0 ? prev_src : 0);
+    Last before = shfl_last<kAttr>(mine, prev_src >= 0 ? prev_src : 0);
     if (prev_src < 0) before = carry;
     // queue the segments with events
     const bool act = valid && e > 0;
@@ -515,12 +524,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
       Q.x[0][k] = before.xn0;
       Q.x[1][k] = before.xn1;
       Q.x[2][k] = before.xn2;
-      if (kAttr) Q.va[k] = a01 | (before.attr << 16);
+      if constexpr (kAttr) Q.va[k] = a01 | (before.attr << 16);
     }
     q_n += (uint32_t)__popcll(am);
     // carry the chunk's last event
     const int last_src = __shfl(src, 63, 64);
-    if (last_src >= 0) carry = shfl_last(mine, last_src);
+    if (last_src >= 0) carry = shfl_last<kAttr>(mine, last_src);
     g0 += total;
     if (q_n >= 64) {
       walk(q_head, 64);
