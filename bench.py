@@ -29,20 +29,22 @@ COPY_CAL_BYTES = 2 << 30
 
 # HBM bytes the ray caster moves per launch on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-#   python3 bench.py --steps 1 --warmup 0 --no-batch --no-serve --no-cpu-baseline --copy-calibration
-# each scaled by the counter's reading for the appended 2 GiB copy (true bytes /
-# counted bytes). The figure holds for the kernel source it was measured on
-# only: bench reports it when csrc/render.hip still has this sha256, else null.
+#   python3 bench.py --steps 2 --warmup 1 --no-batch --no-serve --no-cpu-baseline
+#       --no-gi --no-vdi --no-update --copy-calibration
+# (the two timed steps' dispatches), each scaled by the counter's reading for
+# the appended 2 GiB copy (true bytes / counted bytes). The figure holds for
+# the kernel source it was measured on only: bench reports it when
+# csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
-    "render_hip_sha256": "02f9ae8849f4b9c84f66cb19bffe98a3d87fca44b4fb0f359f6ba98fc1f6cce1",
-    "bytes_per_launch": 114202958,
+    "render_hip_sha256": "3089df756aabf6bab0a9d51a5353e46c53bd1e7db9a14fbc5413b8378baaaa8b",
+    "bytes_per_launch": 121689359,
 }
 # Counters of the same launch and source, from one rocprofv3 --pmc run
 # (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU
 # SQ_THREAD_CYCLES_VALU TCC_HIT_sum TCC_MISS_sum): L2 hit = hits / (hits +
 # misses); VALU lane use = thread-cycles / (64 x wave instructions); waits =
 # SQ_WAIT_ANY / SQ_WAVE_CYCLES.
-RENDER_COUNTERS = {"l2_hit": 0.820, "valu_lane_use": 0.346, "wait_frac": 0.340}
+RENDER_COUNTERS = {"l2_hit": 0.822, "valu_lane_use": 0.341, "wait_frac": 0.358}
 # fp32 operations of one ray-capsule test (two sphere quadratics, the
 # projected cylinder quadratic and its slab clip), counted from the kernel
 # source; the VALU figure of the roofline is tests x this / launch time.
@@ -423,7 +425,10 @@ def vdi_leg(L, synth, torch, dev, stream, s, cam, lut_op, lut_tr, light, reps=5)
     # the largest per-channel difference from the exact frame
     p = dict(radius=0.4, opaque=False, alpha_stop=0.95, merge_curves=True, shading=2,
              light_dir=light)
-    exact = L.lineset_render(s, cam, lut_tr, stream=stream, **p).clone()
+    with torch.cuda.stream(stream):
+        # (allocated, rendered and copied on the bench stream)
+        exact = L.lineset_render(s, cam, lut_tr, stream=stream, **p).clone()
+    stream.synchronize()
     for depth0 in (1.0, 2.0, 3.0):
         with torch.cuda.stream(stream):
             img = L.lineset_render(s, cam, lut_tr, out=out, stream=stream, accel_depth=depth0, **p)

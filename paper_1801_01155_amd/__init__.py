@@ -124,6 +124,16 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _empty(shape, dtype, stream=None, device="cuda"):
+    """A new device tensor allocated on the stream the library call will use,
+    so torch's allocator does not hand its memory to another stream while
+    that call may still write it."""
+    if stream is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(shape, dtype=dtype, device=device)
+
+
 def _dev(t, dtype):
     if t is None:
         return None
@@ -143,7 +153,7 @@ def _grid3(grid):
 def lineset_grid_setup(xyz, grid, stream=None):
     """Device float [V,3] -> device int32 [V,3] lattice; returns (lattice, lo_scale)."""
     xyz = _dev(xyz, torch.float32)
-    lat = torch.empty(xyz.shape, dtype=torch.int32, device=xyz.device)
+    lat = _empty(xyz.shape, torch.int32, stream, xyz.device)
     ls = (C.c_double * 4)()
     _check(lib().lineset_grid_setup(_ptr(xyz), xyz.shape[0], _grid3(grid), _ptr(lat), ls,
                                     _stream(stream)))
@@ -297,7 +307,7 @@ def lineset_render(ls: LineSet, cam, lut, out=None, stream=None, **params):
     """Renders into a device float tensor [H, W, 4] (premultiplied RGBA)."""
     lut = _dev(lut, torch.float32)
     if out is None:
-        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+        out = _empty((cam.height, cam.width, 4), torch.float32, stream)
     c = camera_struct(cam)
     p = render_params(lut, **params)
     _check(lib().lineset_render(ls.handle, C.byref(c), C.byref(p), _ptr(out), _stream(stream)))
@@ -307,7 +317,7 @@ def lineset_render(ls: LineSet, cam, lut, out=None, stream=None, **params):
 def lineset_render_counted(ls: LineSet, cam, lut, out=None, stream=None, **params):
     lut = _dev(lut, torch.float32)
     if out is None:
-        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+        out = _empty((cam.height, cam.width, 4), torch.float32, stream)
     c = camera_struct(cam)
     p = render_params(lut, **params)
     k = RenderCounters()
@@ -365,7 +375,7 @@ def lineset_export(ls: LineSet, what: int, stream=None) -> torch.Tensor:
          EXPORT_REP_LINES: i.level_off[i.n_levels] if i.has_rep_lines else 0,
          EXPORT_ENDS: i.n_records if i.has_vertex_attr else 0,
          EXPORT_LOD_COLOR: 3 * i.level_off[i.n_levels] if i.has_color else 0}[what]
-    t = torch.empty(max(int(n), 1), dtype=_EXPORT_DTYPE[what], device="cuda")
+    t = _empty(max(int(n), 1), _EXPORT_DTYPE[what], stream)
     _check(lib().lineset_export(ls.handle, what, _ptr(t), t.numel() * t.element_size(), 1,
                                 _stream(stream)))
     return t[:n]

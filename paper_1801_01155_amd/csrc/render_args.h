@@ -45,6 +45,9 @@ struct RenderArgs {
   // are rendered by split_s workgroups each, on 8 / split_s pixel rows, so
   // the waves over the densest part of the image hold fewer rays
   int32_t split_n, split_s;
+  // ordered frames: the first top_n launch positions (the longest measured
+  // tiles) are split four ways, before the split_n ones above
+  int32_t top_n;
   // plain launch order by measured cost (tile_order): workgroup position p
   // renders tile order[p]; null: the ring order above. times (or null):
   // each workgroup adds its duration (10 ns ticks) to its tile's entry

@@ -169,11 +169,16 @@ def test_repeated_views_in_measured_order(medium):
     their measured times (longest first). Every frame must equal the view's
     first one (ring order) bit for bit: two views interleaved, on the default
     stream and on a stream of their own, output cleared to NaN before each
-    frame so that a tile left out would show."""
+    frame so that a tile left out would show. The views cover the frame
+    classes whose longest tiles are split differently: 640x480 (split four
+    ways throughout), 1920x1080 (two ways, the longest tiles in 1, 2 or 4
+    parts as measured) and 3840x2160 (unsplit, the same for the longest)."""
     ls, ref, s = medium
     lut = U.dev(synth.lut_importance_alpha())
     cams = [synth.default_camera((96,) * 3, 640, 480),
-            synth.orbit_cameras((96,) * 3, 1, 31, 600, 520)[0]]
+            synth.orbit_cameras((96,) * 3, 1, 31, 600, 520)[0],
+            synth.orbit_cameras((96,) * 3, 1, 32, 1920, 1080)[0],
+            synth.default_camera((96,) * 3, 3840, 2160)]
     kw = dict(radius=0.4, opaque=False, shading=1)
     first = [L.lineset_render(s, c, lut, **kw).clone() for c in cams]
     torch.cuda.synchronize()
