@@ -75,7 +75,7 @@ def parse():
                     help="skip the view-dependent illumination leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the open-loop serving sweep")
-    ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
+    ap.add_argument("--serve-rates", default="10,25,50,100,200,500,1000,2000",
                     help="Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrivals per rate: max(100, rate * seconds), capped")
