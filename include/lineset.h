@@ -294,6 +294,14 @@ typedef struct {
   float accel_depth;         /* opacity acceleration from this optical depth (0: off; see above) */
 } ls_render_params;
 
+/* Launch order (no effect on the image): a transparent frame with more screen
+ * tiles than the device runs at once records each tile's duration; when the
+ * same stream renders the same view again (same set shape and record count,
+ * camera, image size and parameters), its tiles start longest first and the
+ * 32 longest are split four ways. The library keeps, per (device, stream),
+ * the tile times of the stream's last 64 such views (4 bytes per tile each)
+ * and one ordering buffer, until the process ends; enlarging them
+ * synchronises the stream once. */
 int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,
                    float* rgba_out, void* hip_stream);
 
