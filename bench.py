@@ -620,11 +620,16 @@ def main():
     info = s.info()
     # The timed steps render one view again and again, so from the second
     # frame on its tiles are launched longest first (their times measured the
-    # frame before). A view the stream has not rendered yet starts in the
-    # ring order: the same frame with the eye moved by 1e-3 voxel, 5 times.
+    # frame before). A view the stream has not rendered, nor one near it,
+    # starts in the ring order: the frame with the eye moved back along the
+    # view by 3, 6, ..., 15 % of the grid's diagonal (each a new view).
     first_ms = []
+    fwd = np.asarray(cam.forward, np.float64)
+    fwd /= np.linalg.norm(fwd)
+    diag = float(np.sqrt(3.0)) * grid
     for k in range(5):
-        c2 = dataclasses.replace(cam, eye=(cam.eye[0] + 1e-3 * (k + 1),) + tuple(cam.eye[1:]))
+        eye = np.asarray(cam.eye, np.float64) - fwd * diag * 0.03 * (k + 1)
+        c2 = dataclasses.replace(cam, eye=tuple(float(x) for x in eye.astype(np.float32)))
         e0, e1 = ev(), ev()
         with torch.cuda.stream(stream):
             e0.record(stream)
@@ -632,6 +637,21 @@ def main():
             e1.record(stream)
         stream.synchronize()
         first_ms.append(e0.elapsed_time(e1))
+    # A camera in motion: the view direction turned 0.5 degree per frame
+    # about the vertical axis, 12 frames; each frame after the first is
+    # launched in the order of the previous frame's tile times.
+    moving_ms = []
+    for k in range(12):
+        a = np.radians(0.5 * (k + 1))
+        d = (np.cos(a) * 1.0 - np.sin(a) * 0.8, np.sin(a) * 1.0 + np.cos(a) * 0.8, 0.6)
+        c2 = synth.look_camera((grid,) * 3, cam.width, cam.height, d, w["orthographic"])
+        e0, e1 = ev(), ev()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            L.lineset_render(s, c2, lut, out=out, stream=stream, **rp)
+            e1.record(stream)
+        stream.synchronize()
+        moving_ms.append(e0.elapsed_time(e1))
     render_ms = float(np.mean(phase_ms["render"]))
     render_bytes = cnt["list_bytes"] + 16 * rays
     achieved = render_bytes / (render_ms * 1e-3) / 1e9
@@ -689,6 +709,7 @@ def main():
         "render_mrays_s": rays / (med["render"] * 1e-3) / 1e6,
         "ms_per_frame_render": med["render"],
         "ms_per_frame_render_first_view": float(np.median(first_ms)),
+        "ms_per_frame_render_moving_camera": float(np.median(moving_ms[1:])),
         "roofline": {
             "kernel": "k_render (ray caster)",
             "bound": "hbm",

@@ -297,11 +297,13 @@ typedef struct {
 /* Launch order (no effect on the image): a transparent frame with more screen
  * tiles than the device runs at once records each tile's duration; when the
  * same stream renders the same view again (same set shape and record count,
- * camera, image size and parameters), its tiles start longest first and the
- * 32 longest are split four ways. The library keeps, per (device, stream),
- * the tile times of the stream's last 64 such views (4 bytes per tile each)
- * and one ordering buffer, until the process ends; enlarging them
- * synchronises the stream once. */
+ * camera, image size and parameters), or the view with its camera moved
+ * slightly (eye within 2 % of the grid's diagonal, each camera vector within
+ * 2 degrees and 1 % in length), its tiles start longest first by the times
+ * of that earlier frame and the 32 longest are split four ways. The library
+ * keeps, per (device, stream), the tile times of the stream's last 64 such
+ * views (4 bytes per tile each) and one ordering buffer, until the process
+ * ends; enlarging them synchronises the stream once. */
 int lineset_render(ls_lineset_t set, const ls_camera* cam, const ls_render_params* params,
                    float* rgba_out, void* hip_stream);
 

@@ -1804,6 +1804,40 @@ struct OrderKey {
   int32_t split;
 };
 
+// Same view but for a slightly moved camera: everything else equal, the eye
+// within 2 % of the grid's diagonal and each camera vector within 2 degrees
+// and 1 % in length of the other's.
+bool near_view(const OrderKey& a, const OrderKey& b) {
+  OrderKey x = a, y = b;
+  std::memset(&x.cam, 0, sizeof(x.cam));
+  std::memset(&y.cam, 0, sizeof(y.cam));
+  if (std::memcmp(&x, &y, sizeof(x)) != 0) return false;
+  const ls_camera &p = a.cam, &q = b.cam;
+  if (p.width != q.width || p.height != q.height || p.orthographic != q.orthographic)
+    return false;
+  double diag2 = 0, de2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    diag2 += (double)a.grid[k] * a.grid[k];
+    de2 += ((double)p.eye[k] - q.eye[k]) * ((double)p.eye[k] - q.eye[k]);
+  }
+  if (!(de2 <= 4e-4 * diag2)) return false;
+  const float* const u[3] = {p.forward, p.right, p.up};
+  const float* const w[3] = {q.forward, q.right, q.up};
+  for (int k = 0; k < 3; ++k) {
+    double uu = 0, ww = 0, uw = 0;
+    for (int c = 0; c < 3; ++c) {
+      uu += (double)u[k][c] * u[k][c];
+      ww += (double)w[k][c] * w[k][c];
+      uw += (double)u[k][c] * w[k][c];
+    }
+    if (!(uu > 0 && ww > 0)) return false;
+    const double r = std::sqrt(ww / uu);
+    if (!(r > 0.99 && r < 1.01)) return false;
+    if (!(uw / std::sqrt(uu * ww) >= 0.99939)) return false;   // cos 2 degrees
+  }
+  return true;
+}
+
 struct ViewTimes {
   OrderKey key;
   void* times = nullptr;
@@ -1881,6 +1915,13 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
   int v = -1;
   for (int k = 0; k < (int)so.views.size(); ++k)
     if (std::memcmp(&so.views[k].key, &key, sizeof(key)) == 0) v = k;
+  // else a view with the camera only slightly moved (a camera in motion):
+  // its times order this frame, and the entry follows the camera
+  for (int k = 0; v < 0 && k < (int)so.views.size(); ++k)
+    if (near_view(so.views[k].key, key)) {
+      v = k;
+      so.views[v].key = key;
+    }
   bool repeat = v >= 0;
   if (!repeat) {
     if ((int)so.views.size() < kOrderViews) {

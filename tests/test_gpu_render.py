@@ -200,6 +200,42 @@ def test_repeated_views_in_measured_order(medium):
                 assert torch.equal(out, f), f"view {c.width}x{c.height} frame {rep + 1}"
 
 
+def test_moving_camera_frames(medium):
+    """A camera turning 0.5 degree per frame about the grid's vertical axis:
+    from the second frame on, a frame is launched in the order of the tile
+    times of the frame before (a nearby camera). Each frame must equal its
+    own repeat (the order of its own times) bit for bit, output cleared to
+    NaN first, and match the oracle on sampled pixels."""
+    ls, ref, s = medium
+    lut_np = synth.lut_importance_alpha()
+    lut = U.dev(lut_np)
+    kw = dict(radius=0.4, opaque=False, alpha_stop=0.95, merge_curves=True, shading=1)
+    rng = np.random.default_rng(5)
+    st = torch.cuda.Stream()
+    frames = []
+    for k in range(6):
+        a = np.radians(0.5 * k)
+        d = (np.cos(a) * 1.0 - np.sin(a) * 0.8, np.sin(a) * 1.0 + np.cos(a) * 0.8, 0.6)
+        cam = synth.look_camera((96,) * 3, 640, 480, d, False)
+        out = torch.full((cam.height, cam.width, 4), float("nan"), device="cuda")
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            L.lineset_render(s, cam, lut, out=out, stream=st, **kw)
+        st.synchronize()
+        frames.append((cam, out))
+    for k, (cam, out) in enumerate(frames):
+        again = torch.full_like(out, float("nan"))
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            L.lineset_render(s, cam, lut, out=again, stream=st, **kw)
+        st.synchronize()
+        assert torch.equal(out, again), f"frame {k}"
+        img = out.cpu().numpy().reshape(-1, 4)
+        pix = rng.integers(0, cam.width * cam.height, 1500).astype(np.int64)
+        r, _ = O.render(ref, 96, 32, cam, pixels=pix, lut=lut_np, **kw)
+        U.assert_image_parity(img[pix], r, f"moving camera frame {k} sampled pixels")
+
+
 # --- bounded merge table -----------------------------------------------------------------
 def _bundle_along_z(n, grid=16):
     """n straight lines along z (the view direction below) through a bundle of
