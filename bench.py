@@ -36,8 +36,8 @@ COPY_CAL_BYTES = 2 << 30
 # the kernel source it was measured on only: bench reports it when
 # csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
-    "render_hip_sha256": "3089df756aabf6bab0a9d51a5353e46c53bd1e7db9a14fbc5413b8378baaaa8b",
-    "bytes_per_launch": 121689359,
+    "render_hip_sha256": "99773178f28b2d1bd3b99a0644001fc674dc674d586e111607c02f325595aa93",
+    "bytes_per_launch": 122011953,
 }
 # Counters of the same launch and source, from one rocprofv3 --pmc run
 # (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU
