@@ -75,12 +75,12 @@ def parse():
                     help="skip the view-dependent illumination leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the open-loop serving sweep")
-    ap.add_argument("--serve-rates", default="10,25,50,100,200,500,1000,2000",
+    ap.add_argument("--serve-rates", default="10,25,50,100,200,500,1000,2000,4000",
                     help="Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrivals per rate: max(100, rate * seconds), capped")
     ap.add_argument("--serve-max-requests", type=int, default=2000)
-    ap.add_argument("--serve-arena-mib", type=float, default=36.0,
+    ap.add_argument("--serve-arena-mib", type=float, default=128.0,
                     help="server-owned output arena (HBM budget beyond the resident sets)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="append one 2 GiB device-to-device copy (the reference kernel "
