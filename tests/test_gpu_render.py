@@ -179,15 +179,17 @@ def test_repeated_views_in_measured_order(medium):
             synth.orbit_cameras((96,) * 3, 1, 31, 600, 520)[0],
             synth.orbit_cameras((96,) * 3, 1, 32, 1920, 1080)[0],
             synth.default_camera((96,) * 3, 3840, 2160)]
-    kw = dict(radius=0.4, opaque=False, shading=1)
-    first = [L.lineset_render(s, c, lut, **kw).clone() for c in cams]
+    # (the last view also in neighbour mode)
+    views = [(c, dict(radius=0.4, opaque=False, shading=1)) for c in cams]
+    views.append((cams[2], dict(radius=0.4, opaque=False, shading=1, mode=1)))
+    first = [L.lineset_render(s, c, lut, **kw).clone() for c, kw in views]
     torch.cuda.synchronize()
     for f in first:
         assert float(f[..., 3].mean()) > 0.02
     side = torch.cuda.Stream()
     for st in (None, side):
         for rep in range(3):
-            for c, f in zip(cams, first):
+            for (c, kw), f in zip(views, first):
                 out = torch.full((c.height, c.width, 4), float("nan"), device="cuda")
                 if st is not None:
                     st.wait_stream(torch.cuda.current_stream())
@@ -197,7 +199,7 @@ def test_repeated_views_in_measured_order(medium):
                 else:
                     L.lineset_render(s, c, lut, out=out, **kw)
                     torch.cuda.synchronize()
-                assert torch.equal(out, f), f"view {c.width}x{c.height} frame {rep + 1}"
+                assert torch.equal(out, f), f"view {c.width}x{c.height} {kw} frame {rep + 1}"
 
 
 def test_moving_camera_frames(medium):
