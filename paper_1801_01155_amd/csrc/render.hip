@@ -1553,11 +1553,12 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
 // decreasing bucket (k_tile_order), so the longest start first and are the
 // ones split.
 constexpr int kCostBuckets = 256;
-// Ordered frames whose first tiles split two ways split their kTopTiles
-// longest four ways. Measured on the scale workload's 1080p frame (render
-// 0.89 ms unordered-split): 32 -> 0.815, 64 -> 0.819, 256 -> 0.845, 1024 ->
-// 0.953 ms, every split tile four ways -> 1.37 ms; batch-workload views
-// rendered one at a time moved by +1 % at 32.
+// Ordered frames split their kTopTiles longest tiles four ways (unless all
+// their first tiles split four ways already). Measured on the scale
+// workload's 1080p frame (split two ways; render 0.89 ms): 32 -> 0.815, 64
+// -> 0.819, 256 -> 0.845, 1024 -> 0.953 ms, every split tile four ways ->
+// 1.37 ms; batch-workload views rendered one at a time moved by +1 % at 32.
+// On the unsplit 512^3 global-illumination 1080p frame: 2.0 -> 1.46 ms.
 constexpr int kTopTiles = 32;
 
 __device__ inline int cost_bucket(uint32_t c) {
@@ -1957,9 +1958,13 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
                        hist, cursor, order);
     LS_HIP(hipGetLastError());
     R.order = order;
+    // the longest measured tiles split four ways (frames split two ways or
+    // not at all; the light frames split four ways throughout already)
     if (R.split_s == 2) {
       R.top_n = std::min(kTopTiles, R.split_n);
       R.split_n -= R.top_n;
+    } else if (R.split_s == 1) {
+      R.top_n = (int)std::min<int64_t>(kTopTiles, n);
     }
   } else {
     if ((rc = fill_u32(times, 0u, n, st))) return rc;
