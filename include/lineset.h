@@ -294,7 +294,7 @@ typedef struct {
   float accel_depth;         /* opacity acceleration from this optical depth (0: off; see above) */
 } ls_render_params;
 
-/* Launch order (no effect on the image): a transparent frame with more screen
+/* Launch order (no effect on the image): a frame with more screen
  * tiles than the device runs at once records each tile's duration; when the
  * same stream renders the same view again (same set shape and record count,
  * camera, image size and parameters), or the view with its camera moved
