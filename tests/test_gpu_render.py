@@ -179,9 +179,10 @@ def test_repeated_views_in_measured_order(medium):
             synth.orbit_cameras((96,) * 3, 1, 31, 600, 520)[0],
             synth.orbit_cameras((96,) * 3, 1, 32, 1920, 1080)[0],
             synth.default_camera((96,) * 3, 3840, 2160)]
-    # (the last view also in neighbour mode)
+    # (the 1920x1080 view also in neighbour mode, and opaque)
     views = [(c, dict(radius=0.4, opaque=False, shading=1)) for c in cams]
     views.append((cams[2], dict(radius=0.4, opaque=False, shading=1, mode=1)))
+    views.append((cams[2], dict(radius=0.4, opaque=True, shading=1)))
     first = [L.lineset_render(s, c, lut, **kw).clone() for c, kw in views]
     torch.cuda.synchronize()
     for f in first:
