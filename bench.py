@@ -36,8 +36,8 @@ COPY_CAL_BYTES = 2 << 30
 # the kernel source it was measured on only: bench reports it when
 # csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
-    "render_hip_sha256": "1ada7b71ec6170947320cfff86da556adfc4270e70be90452e312c3fbed962be",
-    "bytes_per_launch": 121671966,
+    "render_hip_sha256": "1af6660a94bb1051af3d5efff3425ee3dcda8348ae63b25cb67fe0964b0b0328",
+    "bytes_per_launch": 121560092,
 }
 # Counters of the same launch and source, from one rocprofv3 --pmc run
 # (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU
