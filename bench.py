@@ -37,7 +37,7 @@ COPY_CAL_BYTES = 2 << 30
 # csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
     "render_hip_sha256": "1af6660a94bb1051af3d5efff3425ee3dcda8348ae63b25cb67fe0964b0b0328",
-    "bytes_per_launch": 121560092,
+    "bytes_per_launch": 121683084,
 }
 # Counters of the same launch and source, from one rocprofv3 --pmc run
 # (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU

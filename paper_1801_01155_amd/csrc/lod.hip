@@ -43,6 +43,12 @@ __global__ __launch_bounds__(kBlock) void k_lod0(const uint32_t* offsets, const 
     lo = offsets[v];
     hi = offsets[v + 1];
   }
+  // the transfer function's opacities, staged once per block (a record's
+  // opacity is then not a global load that waits for the record)
+  static_assert(kBlock == 256, "one thread per transfer-function entry");
+  __shared__ float s_alpha[256];
+  s_alpha[threadIdx.x] = opaque ? 1.f : lut[4 * threadIdx.x + 3];
+  __syncthreads();
   const uint32_t n = hi - lo;
   // exclusive scan of the list lengths: this voxel's lines are the wave's
   // lines [P, P + n), i.e. records lo0 + [P, P + n)
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_lod0(const uint32_t* offsets, const 
       decode_point((uint32_t)((rec >> 15) & 0x7FFFu), inv_bins, b);
       const float dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
       L = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float sigma = opaque ? 1.f : lut[4 * ((rec >> 32) & 0xFF) + 3];
+      const float sigma = s_alpha[(rec >> 32) & 0xFF];
       Ls = L * sigma;
     }
     // segmented inclusive scan: lanes of one owner form a contiguous run
