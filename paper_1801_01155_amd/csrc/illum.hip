@@ -422,15 +422,35 @@ __global__ __launch_bounds__(kColThreads) void k_cones_col(Pyramid P, Cones C, S
 #pragma unroll
   for (int i = 0; i < kColZ; ++i) sum[i] = 0.f;
   float occ[kColZ];
+  // the next cone's x/y taps are loaded while the current one is sampled
+  Tap ntx[kN], nty[kN];
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    ntx[k] = C.n > 0 ? xyt[2 * kColTab * k + px] : Tap{0, 0.f};
+    nty[k] = C.n > 0 ? xyt[2 * kColTab * k + kColTab + py] : Tap{0, 0.f};
+  }
   for (int c = 0; c < C.n; ++c) {
-    const Tap* tc = xyt + 2 * kColTab * kN * c;
     const ZRec* zc = zt + kN * c;
+    Tap ctx[kN], cty[kN];
+#pragma unroll
+    for (int k = 0; k < kN; ++k) {
+      ctx[k] = ntx[k];
+      cty[k] = nty[k];
+    }
+    if (c + 1 < C.n) {
+      const Tap* tn = xyt + 2 * kColTab * kN * (c + 1);
+#pragma unroll
+      for (int k = 0; k < kN; ++k) {
+        ntx[k] = tn[2 * kColTab * k + px];
+        nty[k] = tn[2 * kColTab * k + kColTab + py];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < kColZ; ++i) occ[i] = 0.f;
 #pragma unroll
     for (int k = 0; k < kN; ++k) {
       const ZRec z = zc[k];
-      const Tap tx = tc[2 * kColTab * k + px], ty = tc[2 * kColTab * k + kColTab + py];
+      const Tap tx = ctx[k], ty = cty[k];
       const bool in_xy = vx >= z.lo[0] && vx <= z.hi[0] && vy >= z.lo[1] && vy <= z.hi[1];
       const float Dm = in_xy ? S.D[k] : 0.f;
       const int q = CL.slot[k];
