@@ -361,6 +361,16 @@ __device__ inline uint32_t last_event(const int32_t P0[3], const int32_t P1[3],
   return cross;
 }
 
+// Brick-major index of voxel (x, y, z): bricks of 8^3 voxels, nbx bricks
+// along x and nbxy in a z layer of bricks; inside a brick x fastest. A curve's
+// consecutive voxels then share cache lines of a per-voxel array far more
+// often than in row-major order, where a step in z jumps a whole layer.
+__device__ inline uint32_t brick_index(uint32_t x, uint32_t y, uint32_t z, uint32_t nbx,
+                                       uint32_t nbxy) {
+  return (((x >> 3) + nbx * (y >> 3) + nbxy * (z >> 3)) << 9) |
+         ((x & 7u) | (y & 7u) << 3 | (z & 7u) << 6);
+}
+
 // Segments with events wait in a per-wave ring in LDS until 64 of them
 // (or the curve's last ones) can be walked together, so the event walk runs
 // on full waves instead of on the lanes of each 64-segment chunk that happen
@@ -398,7 +408,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
                                                  GridArgs ga, const uint64_t* slot_off,
                                                  uint64_t* rec_out, uint16_t* ends_out,
                                                  uint32_t* vox_out, uint32_t* rank_out,
-                                                 uint32_t* hist) {
+                                                 uint32_t* hist, uint32_t hist_nbx,
+                                                 uint32_t hist_nbxy) {
   using Ring = std::conditional_t<kAttr, EmitRingAttr, EmitRing>;
   __shared__ Ring rings[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
@@ -456,7 +467,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_emit(const float* xyz, const int3
             }
             rec_out[w] = (uint64_t)prev_entry | ((uint64_t)ev.exit_code << 15) | hb;
             vox_out[w] = vid;
-            rank_out[w] = atomicAdd(hist + vid, 1u);
+            const uint32_t hv =
+                hist_nbx ? brick_index(cell[0], cell[1], cell[2], hist_nbx, hist_nbxy) : vid;
+            rank_out[w] = atomicAdd(hist + hv, 1u);
           }
         }
       }
@@ -551,6 +564,36 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* vox, const u
   uint32_t v = vox[e];
   if (v == LS_INVALID_VOXEL) return;
   idx[offsets[v] + rank[e]] = ((uint64_t)v << 32) | (uint32_t)e;
+}
+
+struct BrickGrid {
+  int32_t g[3];          // voxel grid (row-major ids)
+  uint32_t nbx, nbxy;    // brick grid (brick_index)
+};
+
+// Brick-major -> row-major copy of a per-voxel array. A workgroup moves 8
+// bricks consecutive along x (4096 words, one contiguous read) through LDS
+// and writes their 64 rows of up to 64 voxels (contiguous writes); grid
+// (ceil(nbx / 8), bricks along y, bricks along z).
+constexpr int kRunBricks = 8;
+
+__global__ __launch_bounds__(kBlock) void k_from_bricks(const uint32_t* brick, BrickGrid bg,
+                                                        uint32_t* rows) {
+  __shared__ uint32_t s_b[kRunBricks * 513];   // one padding word per brick: no bank conflicts
+  const uint32_t bx0 = blockIdx.x * kRunBricks, by = blockIdx.y, bz = blockIdx.z;
+  const uint32_t nb = bg.nbx - bx0 < (uint32_t)kRunBricks ? bg.nbx - bx0 : kRunBricks;
+  const uint32_t* src = brick + ((size_t)(bx0 + bg.nbx * by + bg.nbxy * bz) << 9);
+  for (uint32_t i = threadIdx.x; i < nb * 512; i += kBlock) s_b[(i >> 9) * 513 + (i & 511)] = src[i];
+  __syncthreads();
+  const int32_t x0 = 8 * (int32_t)bx0;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < 64 * 64; i += kBlock) {
+    const int xx = i & 63, row = i >> 6;
+    const int32_t x = x0 + xx, y = 8 * (int32_t)by + (row & 7), z = 8 * (int32_t)bz + (row >> 3);
+    if (x < bg.g[0] && y < bg.g[1] && z < bg.g[2])
+      rows[x + (int64_t)bg.g[0] * (y + (int64_t)bg.g[1] * z)] =
+          s_b[(xx >> 3) * 513 + ((xx & 7) | (row & 7) << 3 | (row >> 3) << 6)];
+  }
 }
 
 // Each CSR slot p holds some emitted line e of voxel v; its final position is
@@ -775,6 +818,11 @@ __global__ __launch_bounds__(kBlock) void k_snap(const float* xyz, int64_t nv, S
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Grids from this many voxels count lines in brick-major order: their 4-byte
+// per-voxel array (128 MiB and up) no longer sits comfortably in the 256 MB
+// last-level cache, so the emit's row-major atomics would go to HBM at random.
+constexpr int64_t kBrickMinVoxels = int64_t(1) << 25;
 inline unsigned curve_blocks(int64_t n) {
   return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock);
 }
@@ -939,9 +987,25 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
   }
   s->n_slots = (int64_t)n_slots;
 
-  // 2. offsets array (owned by the set) doubles as the histogram
+  // 2. offsets array (owned by the set) doubles as the histogram; on grids
+  // whose per-voxel array outgrows the last-level cache the lines are counted
+  // in a brick-major array instead (the emit's atomics then follow a curve
+  // through nearby cache lines), copied to row-major order before the scan
   if ((rc = ls_alloc(s, (void**)&s->offsets, sizeof(uint32_t) * (s->nvox + 1)))) return rc;
-  if ((rc = fill_u32(s->offsets, 0u, s->nvox + 1, st))) return rc;
+  const bool bricks = s->nvox >= kBrickMinVoxels;
+  BrickGrid bg{};
+  for (int a = 0; a < 3; ++a) bg.g[a] = s->grid[a];
+  DeviceBuf hist_b(st);
+  if (bricks) {
+    bg.nbx = (uint32_t)(s->grid[0] + 7) / 8;
+    bg.nbxy = bg.nbx * (uint32_t)((s->grid[1] + 7) / 8);
+    const int64_t nb = (int64_t)bg.nbxy * ((s->grid[2] + 7) / 8) * 512;
+    if ((rc = hist_b.alloc(sizeof(uint32_t) * nb))) return rc;
+    if ((rc = fill_u32(hist_b.as<uint32_t>(), 0u, nb, st))) return rc;
+  } else if ((rc = fill_u32(s->offsets, 0u, s->nvox + 1, st))) {
+    return rc;
+  }
+  uint32_t* hist = bricks ? hist_b.as<uint32_t>() : s->offsets;
 
   // 3. emit
   DeviceBuf rec(st), vox(st), rank(st), sums32(st), ends_slots(st);
@@ -958,26 +1022,33 @@ int vox_build(ls_lineset* s, const float* xyz, const int32_t* lat, const int64_t
       hipLaunchKernelGGL((k_emit<true, true>), grid, block, 0, st, xyz, lat, curve_off, attr,
                          vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
                          rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
-                         s->offsets);
+                         hist, bg.nbx, bg.nbxy);
     else if (float_in)
       hipLaunchKernelGGL((k_emit<true, false>), grid, block, 0, st, xyz, lat, curve_off, attr,
                          vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
                          rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
-                         s->offsets);
+                         hist, bg.nbx, bg.nbxy);
     else if (vattr)
       hipLaunchKernelGGL((k_emit<false, true>), grid, block, 0, st, xyz, lat, curve_off, attr,
                          vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
                          rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
-                         s->offsets);
+                         hist, bg.nbx, bg.nbxy);
     else
       hipLaunchKernelGGL((k_emit<false, false>), grid, block, 0, st, xyz, lat, curve_off, attr,
                          vattr, C, s->curve_base, sad, ga, slots.as<uint64_t>(),
                          rec.as<uint64_t>(), eo, vox.as<uint32_t>(), rank.as<uint32_t>(),
-                         s->offsets);
+                         hist, bg.nbx, bg.nbxy);
     LS_HIP(hipGetLastError());
   }
 
   // 4. counts -> offsets (in place)
+  if (bricks) {
+    const dim3 grid((bg.nbx + kRunBricks - 1) / kRunBricks, (s->grid[1] + 7) / 8,
+                    (s->grid[2] + 7) / 8);
+    hipLaunchKernelGGL(k_from_bricks, grid, dim3(kBlock), 0, st, hist_b.as<uint32_t>(), bg,
+                       s->offsets);
+    LS_HIP(hipGetLastError());
+  }
   if ((rc = exclusive_scan_u32(s->offsets, s->offsets, s->nvox, sums32.as<uint32_t>(), st)))
     return rc;
   uint32_t n_rec = 0;

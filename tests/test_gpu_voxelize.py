@@ -75,6 +75,24 @@ def test_voxelize_medium_perturbed_and_deterministic():
     _csr_equal(b, ref, "medium lattice")
 
 
+def test_voxelize_brick_counting_grid():
+    # grids from 2^25 voxels count lines per voxel in brick-major (8^3) order;
+    # sides that are not multiples of 8 leave partial bricks at the far faces
+    grid = (517, 262, 251)
+    assert grid[0] * grid[1] * grid[2] >= 1 << 25
+    ls = synth.abc_lineset(3000, 200, 12, perturb=True)
+    ref, lat = U.oracle_csr_from_xyz(ls, grid, 32)
+    a = L.lineset_voxelize(ls.curve_off, grid, 32, xyz=ls.xyz, attr=ls.attr)
+    _csr_equal(a, ref, "brick grid xyz")
+    rng = np.random.default_rng(11)
+    lat2, off2 = _random_curves(rng, 2000, grid, 16)
+    b = L.lineset_voxelize(off2, grid, 8, lattice=lat2)
+    _csr_equal(b, O.voxelize(lat2, off2, None, grid, 8), "brick grid random")
+    info = b.info()
+    cnt = np.diff(O.voxelize(lat2, off2, None, grid, 8).offsets.astype(np.int64))
+    assert info.nonempty_voxels == int((cnt > 0).sum()) and info.max_list == int(cnt.max())
+
+
 def test_voxelize_degenerate_inputs():
     # no curves, single-vertex curves, curves that never leave a voxel
     grid = (8, 8, 8)
