@@ -300,7 +300,8 @@ typedef struct {
  * camera, image size and parameters), or the view with its camera moved
  * slightly (eye within 2 % of the grid's diagonal, each camera vector within
  * 2 degrees and 1 % in length), its tiles start longest first by the times
- * of that earlier frame and the 32 longest are split four ways. The library
+ * of that earlier frame and the 32 longest are split four ways (eight ways
+ * in frames that split no other tile). The library
  * keeps, per (device, stream), the tile times of the stream's last 64 such
  * views (4 bytes per tile each) and one ordering buffer, until the process
  * ends; enlarging them synchronises the stream once. */

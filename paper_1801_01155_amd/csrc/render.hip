@@ -1379,14 +1379,14 @@ __global__ __launch_bounds__(kBlock) void k_render(RenderArgs R) {
     // dealt to the XCDs round-robin, so in a full group the parts of a tile
     // share an XCD (and its L2) as its lists are read again
     int first = 0;   // launch positions before this region
-    if (b < 4 * R.top_n) {
-      nsub = 4;
+    if (b < R.top_s * R.top_n) {
+      nsub = R.top_s;
       const int grp = b / (kXcds * nsub), r = b - grp * kXcds * nsub;
       const int w = min(kXcds, R.top_n - grp * kXcds);   // tiles in the group
       sub = r / w;
       b = grp * kXcds + r % w;
     } else {
-      b -= 4 * R.top_n;
+      b -= R.top_s * R.top_n;
       first = R.top_n;
       if (R.split_s > 1) {
         const int ns = R.split_n * R.split_s;
@@ -1553,13 +1553,15 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(const RenderArgs* __res
 // decreasing bucket (k_tile_order), so the longest start first and are the
 // ones split.
 constexpr int kCostBuckets = 256;
-// Ordered frames split their kTopTiles longest tiles four ways (unless all
-// their first tiles split four ways already). Measured on the scale
-// workload's 1080p frame (split two ways; render 0.89 ms): 32 -> 0.815, 64
-// -> 0.819, 256 -> 0.845, 1024 -> 0.953 ms, every split tile four ways ->
-// 1.37 ms; batch-workload views rendered one at a time moved by +1 % at 32.
-// On the unsplit 512^3 global-illumination 1080p frame: 2.0 -> 1.46 ms;
-// opaque frames (unsplit), batch-workload sets 12-18 % faster.
+// Ordered frames split their kTopTiles longest tiles four ways (frames split
+// two ways) or eight ways (frames not split; frames split four ways
+// throughout keep that). Measured on the scale workload's 1080p frame (split
+// two ways; render 0.89 ms): 32 -> 0.815, 64 -> 0.819, 256 -> 0.845, 1024 ->
+// 0.953 ms, every split tile four ways -> 1.37 ms; eight ways: 0.81 (16, 32
+// tiles), 0.85 ms for the moving camera; batch-workload views rendered one at
+// a time moved by +1 % at 32. On the unsplit 512^3 global-illumination 1080p
+// frame: 2.0 -> 1.46 ms (four ways), 1.22 ms (eight ways; 64 tiles the same);
+// opaque frames (unsplit), batch-workload sets 12-18 % faster (four ways).
 constexpr int kTopTiles = 32;
 
 __device__ inline int cost_bucket(uint32_t c) {
@@ -1696,6 +1698,7 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
   R.spiral_r = -1;
   R.order = nullptr;
   R.top_n = 0;
+  R.top_s = 4;
   R.split_n = 0;
   R.split_s = 1;
   {
@@ -1757,7 +1760,7 @@ int make_render_args(const ls_lineset* s, const ls_camera* cam, const ls_render_
 int launch_render(const RenderArgs& R, hipStream_t st) {
   const int tiles_y = R.n_tiles / R.tiles_x;
   const unsigned blocks =
-      R.order ? (unsigned)(R.n_tiles + 3 * R.top_n + R.split_n * (R.split_s - 1))
+      R.order ? (unsigned)(R.n_tiles + (R.top_s - 1) * R.top_n + R.split_n * (R.split_s - 1))
       : R.spiral_r >= 0 ? (unsigned)((2 * R.spiral_r + 1) * (2 * R.spiral_r + 1) +
                                      R.split_n * (R.split_s - 1))
                         : (unsigned)(kXcds * ((tiles_y + kXcds - 1) / kXcds) * R.tiles_x);
@@ -1957,13 +1960,16 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
                        hist, cursor, order);
     LS_HIP(hipGetLastError());
     R.order = order;
-    // the longest measured tiles split four ways (frames split two ways or
-    // not at all; the light frames split four ways throughout already)
+    // the longest measured tiles split four ways in frames split two ways,
+    // eight ways in frames not split at all (the light frames split four
+    // ways throughout already)
     if (R.split_s == 2) {
       R.top_n = std::min(kTopTiles, R.split_n);
+      R.top_s = 4;
       R.split_n -= R.top_n;
     } else if (R.split_s == 1) {
       R.top_n = (int)std::min<int64_t>(kTopTiles, n);
+      R.top_s = 8;
     }
   } else {
     if ((rc = fill_u32(times, 0u, n, st))) return rc;

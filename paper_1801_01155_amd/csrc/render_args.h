@@ -46,8 +46,8 @@ struct RenderArgs {
   // the waves over the densest part of the image hold fewer rays
   int32_t split_n, split_s;
   // ordered frames: the first top_n launch positions (the longest measured
-  // tiles) are split four ways, before the split_n ones above
-  int32_t top_n;
+  // tiles) are split top_s ways (4 or 8), before the split_n ones above
+  int32_t top_n, top_s;
   // plain launch order by measured cost (tile_order): workgroup position p
   // renders tile order[p]; null: the ring order above. times (or null):
   // each workgroup adds its duration (10 ns ticks) to its tile's entry
