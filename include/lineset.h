@@ -295,7 +295,9 @@ typedef struct {
 } ls_render_params;
 
 /* Launch order (no effect on the image): a frame with more screen
- * tiles than the device runs at once records each tile's duration; when the
+ * tiles than the device runs at once records each tile's duration (the
+ * first frame of a transparent view starts its tiles in the order of a cost
+ * estimate from the occupancy words along four rays per tile); when the
  * same stream renders the same view again (same set shape and record count,
  * camera, image size and parameters), or the view with its camera moved
  * slightly (eye within 2 % of the grid's diagonal, each camera vector within

@@ -1592,6 +1592,55 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const uint32_t* __restrict
   if (h[threadIdx.x]) atomicAdd(hist + threadIdx.x, h[threadIdx.x]);
 }
 
+// The first frame of a transparent view has no measured times: each tile's
+// cost is estimated instead from the occupancy words its rays cross, four
+// rays per tile (at the centres of its quadrants), one sample per macro-cell
+// length between grid entry and exit, adding the non-empty voxels of the
+// sampled macro cell. Only the launch order depends on it.
+constexpr int kProbeRays = 4;
+
+__global__ __launch_bounds__(kBlock) void k_tile_probe(RenderArgs R, uint32_t* __restrict__ cost) {
+  const int t = blockIdx.x * (kBlock / kProbeRays) + (int)threadIdx.x / kProbeRays;
+  const int r = threadIdx.x % kProbeRays;
+  uint32_t c = 0;
+  if (t < R.n_tiles) {
+    const int tw = 8 * R.wx, th = 8 * R.wy;
+    const int i = min((t % R.tiles_x) * tw + ((r & 1) ? 3 * tw / 4 : tw / 4), R.W - 1);
+    const int j = min((t / R.tiles_x) * th + ((r & 2) ? 3 * th / 4 : th / 4), R.H - 1);
+    float o[3], d[3];
+    make_ray(R, i, j, o, d);
+    float tn = 0.f, tf = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] != 0.f) {
+        const float inv = 1.f / d[a];
+        const float ta = -o[a] * inv, tb = ((float)R.g[a] - o[a]) * inv;
+        tn = fmaxf(tn, fminf(ta, tb));
+        tf = fminf(tf, fmaxf(ta, tb));
+      } else if (!(o[a] >= 0.f && o[a] < (float)R.g[a])) {
+        tf = -1.f;
+      }
+    }
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (tn < tf && len > 0.f) {
+      const float dt = 4.f / len;
+      const int steps = (int)fminf((tf - tn) / dt + 1.f, 4096.f);
+#pragma unroll 4
+      for (int k = 0; k < steps; ++k) {
+        const float tt = tn + ((float)k + 0.5f) * dt;
+        int m[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          m[a] = min(max((int)floorf(o[a] + tt * d[a]) >> 2, 0), R.mg[a] - 1);
+        c += (uint32_t)__popcll(R.occ[m[0] + (int64_t)R.mg[0] * (m[1] + (int64_t)R.mg[1] * m[2])]);
+      }
+    }
+  }
+  c += __shfl_xor(c, 1);
+  c += __shfl_xor(c, 2);
+  if (r == 0 && t < R.n_tiles) cost[t] = c;
+}
+
 // order[p]: the tile at position p, by decreasing bucket (the order inside a
 // bucket depends on atomic order; every tile appears once). Clears the
 // times for the frame about to be measured.
@@ -1951,7 +2000,14 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
   uint32_t* cursor = hist + kCostBuckets;
   int32_t* order = reinterpret_cast<int32_t*>(cursor + kCostBuckets);
   uint8_t* bucket = reinterpret_cast<uint8_t*>(order + n);
-  if (repeat) {
+  // first frame of a transparent view: estimated costs order it
+  const bool probe = !repeat && !R.opaque;
+  if (probe) {
+    const unsigned pb = (unsigned)((n + kBlock / kProbeRays - 1) / (kBlock / kProbeRays));
+    hipLaunchKernelGGL(k_tile_probe, dim3(pb), dim3(kBlock), 0, st, R, times);
+    LS_HIP(hipGetLastError());
+  }
+  if (repeat || probe) {
     if ((rc = fill_u32(hist, 0u, 2 * kCostBuckets, st))) return rc;
     const unsigned tb = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_tile_hist, dim3(tb), dim3(kBlock), 0, st, times, (int32_t)n, bucket,
@@ -1962,8 +2018,13 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
     R.order = order;
     // the longest measured tiles split four ways in frames split two ways,
     // eight ways in frames not split at all (the light frames split four
-    // ways throughout already)
-    if (R.split_s == 2) {
+    // ways throughout already). Not in an estimated frame: a split tile's
+    // parts add their durations, up to nsub times the tile's unsplit
+    // duration (each part takes about as long as its slowest ray), which
+    // keeps the longest tiles on top once measured but would keep tiles the
+    // estimate wrongly put on top there too.
+    if (probe) {
+    } else if (R.split_s == 2) {
       R.top_n = std::min(kTopTiles, R.split_n);
       R.top_s = 4;
       R.split_n -= R.top_n;
