@@ -36,15 +36,15 @@ COPY_CAL_BYTES = 2 << 30
 # the kernel source it was measured on only: bench reports it when
 # csrc/render.hip still has this sha256, else null.
 RENDER_TRAFFIC = {
-    "render_hip_sha256": "4b9596b7baaf164a14b89dea792cef0e5763f16375aef8647bdc8363eb883112",
-    "bytes_per_launch": 121719776,
+    "render_hip_sha256": "57708021c185b83ec7d01373ce499af607c3c09f6ba1bff7b17d4d6f946dd193",
+    "bytes_per_launch": 122445904,
 }
 # Counters of the same launch and source, from one rocprofv3 --pmc run
 # (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_VALU
 # SQ_THREAD_CYCLES_VALU TCC_HIT_sum TCC_MISS_sum): L2 hit = hits / (hits +
 # misses); VALU lane use = thread-cycles / (64 x wave instructions); waits =
 # SQ_WAIT_ANY / SQ_WAVE_CYCLES.
-RENDER_COUNTERS = {"l2_hit": 0.822, "valu_lane_use": 0.341, "wait_frac": 0.351}
+RENDER_COUNTERS = {"l2_hit": 0.822, "valu_lane_use": 0.341, "wait_frac": 0.350}
 # fp32 operations of one ray-capsule test (two sphere quadratics, the
 # projected cylinder quadratic and its slab clip), counted from the kernel
 # source; the VALU figure of the roofline is tests x this / launch time.

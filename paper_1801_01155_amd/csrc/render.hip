@@ -1596,12 +1596,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const uint32_t* __restrict
 // cost is estimated instead from the occupancy words its rays cross, four
 // rays per tile (at the centres of its quadrants), one sample per macro-cell
 // length between grid entry and exit, adding the non-empty voxels of the
-// sampled macro cell. Only the launch order depends on it.
-constexpr int kProbeRays = 4;
+// sampled macro cell. Only the launch order depends on it. Each ray's
+// samples are shared by kProbeSegs lanes (every kProbeSegs-th sample).
+constexpr int kProbeRays = 4, kProbeSegs = 4, kProbeLanes = kProbeRays * kProbeSegs;
 
 __global__ __launch_bounds__(kBlock) void k_tile_probe(RenderArgs R, uint32_t* __restrict__ cost) {
-  const int t = blockIdx.x * (kBlock / kProbeRays) + (int)threadIdx.x / kProbeRays;
-  const int r = threadIdx.x % kProbeRays;
+  const int t = blockIdx.x * (kBlock / kProbeLanes) + (int)threadIdx.x / kProbeLanes;
+  const int l = threadIdx.x % kProbeLanes, r = l % kProbeRays, seg = l / kProbeRays;
   uint32_t c = 0;
   if (t < R.n_tiles) {
     const int tw = 8 * R.wx, th = 8 * R.wy;
@@ -1625,8 +1626,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_probe(RenderArgs R, uint32_t* _
     if (tn < tf && len > 0.f) {
       const float dt = 4.f / len;
       const int steps = (int)fminf((tf - tn) / dt + 1.f, 4096.f);
-#pragma unroll 4
-      for (int k = 0; k < steps; ++k) {
+#pragma unroll 2
+      for (int k = seg; k < steps; k += kProbeSegs) {
         const float tt = tn + ((float)k + 0.5f) * dt;
         int m[3];
 #pragma unroll
@@ -1636,9 +1637,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_probe(RenderArgs R, uint32_t* _
       }
     }
   }
-  c += __shfl_xor(c, 1);
-  c += __shfl_xor(c, 2);
-  if (r == 0 && t < R.n_tiles) cost[t] = c;
+#pragma unroll
+  for (int m = 1; m < kProbeLanes; m <<= 1) c += __shfl_xor(c, m);
+  if (l == 0 && t < R.n_tiles) cost[t] = c;
 }
 
 // order[p]: the tile at position p, by decreasing bucket (the order inside a
@@ -2003,7 +2004,7 @@ int tile_order(const ls_lineset* s, const ls_camera* cam, const ls_render_params
   // first frame of a transparent view: estimated costs order it
   const bool probe = !repeat && !R.opaque;
   if (probe) {
-    const unsigned pb = (unsigned)((n + kBlock / kProbeRays - 1) / (kBlock / kProbeRays));
+    const unsigned pb = (unsigned)((n + kBlock / kProbeLanes - 1) / (kBlock / kProbeLanes));
     hipLaunchKernelGGL(k_tile_probe, dim3(pb), dim3(kBlock), 0, st, R, times);
     LS_HIP(hipGetLastError());
   }
