@@ -63,6 +63,23 @@ def test_records_and_endpoint_attributes_bit_exact(attr_set):
     assert np.array_equal(e2, ref.ends)
 
 
+def test_endpoint_attributes_on_brick_counting_grid(attr_set):
+    # grids from 2^25 voxels count lines in brick-major order (ragged bricks
+    # at the far faces); the attribute instance of the emit pass takes the
+    # same path
+    A = attr_set
+    grid = (517, 262, 251)
+    lat, _, _ = O.grid_setup(A["ls"].xyz, grid)
+    ref = O.voxelize(lat, A["ls"].curve_off, A["ls"].attr, grid, 32, vattr=A["va"])
+    s = L.lineset_voxelize(A["ls"].curve_off, grid, 32, xyz=A["ls"].xyz, attr=A["ls"].attr,
+                           vattr=A["va"])
+    offs, recs = U.gpu_csr(s)
+    ends = L.lineset_export(s, L.EXPORT_ENDS).cpu().numpy().view(np.uint16)
+    print(f"[attributes brick grid] records={len(recs)}", flush=True)
+    assert np.array_equal(offs, ref.offsets) and np.array_equal(recs, ref.records)
+    assert np.array_equal(ends, ref.ends)
+
+
 def test_density_from_mean_attribute(attr_set):
     A = attr_set
     lut = synth.lut_importance_alpha()
