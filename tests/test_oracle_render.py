@@ -169,6 +169,28 @@ def test_exact_mode_equals_bruteforce(seed, opaque, shading):
     assert err.max() < 1e-5 and (err > 1e-7).mean() < 0.01
 
 
+@pytest.mark.parametrize("seed,opaque,shading", [(1, False, 1), (2, True, 1), (5, False, 0),
+                                                 (6, False, 1)])
+def test_own_voxel_mode_equals_bruteforce(seed, opaque, shading):
+    # the own-voxel (fast) mode against its definition written without a grid
+    # walk: voxels by brute-force box tests, their own lines' hits (t_in >= 0)
+    # composited voxel by voxel; tubes wide enough to leave their voxels
+    grid = (6, 5, 7)
+    lat, off, attr = _tiny_set(seed, grid, 6, 10)
+    csr = O.voxelize(lat, off, attr, grid, 16)
+    lut = synth.lut_importance_alpha(0.15, 0.6)
+    cam = synth.orbit_cameras(grid, 1, seed, 24, 20, orthographic=bool(seed % 2))[0]
+    kw = dict(radius=0.35, opaque=opaque, alpha_stop=0.95, merge_curves=True, shading=shading)
+    img, cnt = O.render(csr, grid, 16, cam, mode=0, lut=lut, **kw)
+    ref = RB.render_own_voxel(csr.offsets, csr.records, grid, 16, cam, lut, **kw)
+    assert cnt["fragments"] > 10
+    err = np.abs(img.reshape(-1, 4) - ref).max(1)
+    assert err.max() < 1e-5 and (err > 1e-7).mean() < 0.01
+    # here the own-voxel order is not the exact one, so the pin tells them apart
+    exact, _ = O.render(csr, grid, 16, cam, mode=1, lut=lut, **kw)
+    assert np.abs(img - exact).max() > 1e-3
+
+
 def test_fast_equals_exact_for_thin_separated_tubes():
     # thin tubes never leave their own voxel, so own-voxel lists are complete
     grid = (6, 6, 6)
